@@ -1,0 +1,75 @@
+"""Probability statistics of the amplitude tensor (oracle, float64).
+
+* Linear XEB, Eq. (1): F = 2^n / L * sum_i P(s_i) - 1 over the L computed
+  bitstrings (section "Fidelity").  With s1 fixed and all L = 2^n2 values of
+  s2 weighted equally this is F_unif = 2^n1 * sum P - 1.
+* F_self = 2^n * sum P^2 / sum P - 1: the XEB of bitstrings drawn from P
+  itself; about 1 when the probabilities follow Porter-Thomas, Eq. (2).
+* Post-selection curve: probabilities sorted in decreasing order, the XEB of
+  the top k (section "Fidelity", right panel of Fig. 2).
+* Marginal P(s1) = sum_s2 P(s1; s2) and conditional P(s2 | s1) = P / P(s1)
+  (appendix C): P(s1) = (F_unif + 1) 2^-n1, and the conditional
+  distribution's own XEB is exactly 0.
+* Porter-Thomas checks: Kolmogorov-Smirnov distance of N p against Exp(1)
+  and the second moment E[(N p)^2] = 2.
+* GPU efficiency, Eq. (3): E = 8 * (complex multiply-adds) / (peak * time).
+"""
+
+import numpy as np
+
+
+def probabilities(amps):
+    a = np.asarray(amps, dtype=np.complex128)
+    return a.real ** 2 + a.imag ** 2
+
+
+def xeb(p, n_qubits):
+    """Eq. (1) over all given probabilities, equal weights."""
+    p = np.asarray(p, dtype=np.float64)
+    return (2.0 ** n_qubits) / p.size * p.sum() - 1.0
+
+
+def xeb_self(p, n_qubits):
+    p = np.asarray(p, dtype=np.float64)
+    return (2.0 ** n_qubits) * (p * p).sum() / p.sum() - 1.0
+
+
+def topk_curve(p, n_qubits, ks):
+    s = np.sort(np.asarray(p, dtype=np.float64))[::-1]
+    c = np.cumsum(s)
+    return np.array([(2.0 ** n_qubits) / k * c[k - 1] - 1.0 for k in ks])
+
+
+def marginal(p):
+    return float(np.sum(p))
+
+
+def conditional(p):
+    p = np.asarray(p, dtype=np.float64)
+    return p / p.sum()
+
+
+def pt_ks_distance(p, n_qubits):
+    """sup |F_emp(x) - (1 - e^-x)| for x = 2^n p."""
+    x = np.sort(np.asarray(p, dtype=np.float64) * 2.0 ** n_qubits)
+    m = x.size
+    cdf = 1.0 - np.exp(-x)
+    hi = np.arange(1, m + 1) / m
+    lo = np.arange(0, m) / m
+    return float(max(np.max(np.abs(hi - cdf)), np.max(np.abs(cdf - lo))))
+
+
+def pt_second_moment(p, n_qubits):
+    x = np.asarray(p, dtype=np.float64) * 2.0 ** n_qubits
+    return float(np.mean(x * x))
+
+
+def efficiency(complex_macs, peak_flops, seconds):
+    """Eq. (3): 8 real flops per complex multiply-add."""
+    return 8.0 * complex_macs / (peak_flops * seconds)
+
+
+def norm_rel_error(x, ref):
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))

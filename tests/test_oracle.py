@@ -1,0 +1,293 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: closed
+forms, brute force, an independent implementation of a different method,
+invariants the exact result must satisfy, or numbers printed in the paper
+(tests/golden/paper_numbers.json).  No test here touches the GPU library.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import rqc
+from rqc import gates as G
+from oracle import statevector as sv
+from oracle import unitary
+from oracle import network as nw
+from oracle import closed_form as cf
+from oracle import stats
+from oracle import mlp
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_numbers.json")
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+# --- gate matrices --------------------------------------------------------
+
+def test_gate_closed_forms():
+    i2 = np.eye(2)
+    for name, p in (("X", G.pauli("X")), ("Y", G.pauli("Y")), ("W", G.pauli("W"))):
+        s = G.single_qubit("sqrt_" + name.lower())
+        np.testing.assert_allclose(s.conj().T @ s, i2, atol=1e-15)
+        np.testing.assert_allclose(s @ s, -1j * p, atol=1e-15)
+    np.testing.assert_allclose(G.fsim(0.0, 0.0), np.eye(4), atol=0)
+    f = G.fsim(np.pi / 2, 0.0)
+    e01 = np.array([0, 1, 0, 0], dtype=complex)
+    np.testing.assert_allclose(f @ e01, np.array([0, 0, -1j, 0]), atol=1e-15)
+    g = G.fsim(0.3, 1.1)
+    np.testing.assert_allclose(g.conj().T @ g, np.eye(4), atol=1e-15)
+    assert np.isclose(g[3, 3], np.exp(-1.1j))
+
+
+def test_generator_rules():
+    lay = rqc.rect_layout(5, 8)
+    for k in "ABCD":
+        qs = [q for p in lay.patterns[k] for q in p]
+        assert len(qs) == len(set(qs)), "coupler pattern must be a matching"
+    d = rqc.diag54_layout(0)
+    assert d.n_qubits == 53
+    for k in "ABCD":
+        qs = [q for p in d.patterns[k] for q in p]
+        assert len(qs) == len(set(qs))
+    assert max(len(x) for x in d.neighbours()) <= 4
+    c = rqc.random_circuit(lay, 10, seed=5)
+    prev = {}
+    for g in c.gates:
+        if len(g.qubits) == 1:
+            q = g.qubits[0]
+            assert prev.get(q) != g.label, "no repeated single-qubit gate on a qubit"
+            prev[q] = g.label
+        else:
+            th = math.acos(max(-1.0, min(1.0, g.matrix[1, 1].real)))
+            assert abs(th - np.pi / 2) <= 0.05 + 1e-12
+            ph = -np.angle(g.matrix[3, 3])
+            assert abs(ph - np.pi / 6) <= 0.05 + 1e-12
+    seq = [g.label[-1] for g in c.gates if len(g.qubits) == 2]
+    cycles = []
+    for s in seq:
+        if not cycles or cycles[-1] != s:
+            cycles.append(s)
+    assert "".join(cycles[:8]) == "ABCDCDAB"
+
+
+# --- state vector ---------------------------------------------------------
+
+@pytest.mark.parametrize("shape,cycles,seed", [((2, 2), 4, 0), ((2, 3), 6, 3), ((2, 4), 5, 4), ((1, 3), 3, 9)])
+def test_statevector_vs_bruteforce(shape, cycles, seed):
+    c = rqc.random_circuit(rqc.rect_layout(*shape), cycles, seed=seed)
+    np.testing.assert_allclose(sv.simulate_numpy(c), unitary.state(c), atol=1e-13)
+
+
+def test_statevector_c_vs_numpy():
+    c = rqc.random_circuit(rqc.rect_layout(3, 4), 8, seed=11)
+    np.testing.assert_allclose(sv.simulate_c(c), sv.simulate_numpy(c), atol=1e-13)
+
+
+def test_statevector_norm_and_product_state():
+    c = rqc.random_circuit(rqc.rect_layout(3, 4), 8, seed=2)
+    assert abs(np.linalg.norm(sv.simulate_c(c)) - 1.0) < 1e-12
+    # fSim(0, 0) = identity: the state is the product of single-qubit states
+    c0 = rqc.random_circuit(rqc.rect_layout(2, 3), 4, seed=2, two_qubit="identity")
+    psi = sv.simulate_numpy(c0)
+    vec = np.array([1.0 + 0j])
+    for q in range(6):
+        v = np.array([1.0, 0.0], dtype=complex)
+        for g in c0.gates:
+            if g.qubits == (q,):
+                v = g.matrix @ v
+        vec = np.kron(vec, v)
+    np.testing.assert_allclose(psi, vec, atol=1e-14)
+
+
+# --- network and contraction ---------------------------------------------
+
+def _random_split(n, n_open, seed):
+    rng = np.random.default_rng(seed)
+    open_q = sorted(rng.choice(n, size=n_open, replace=False).tolist())
+    fixed_q = [q for q in range(n) if q not in open_q]
+    bits = rng.integers(0, 2, size=len(fixed_q)).astype(np.uint8)
+    return open_q, fixed_q, bits
+
+
+@pytest.mark.parametrize("n_open", [0, 1, 3, 6, 12])
+def test_network_equals_statevector(n_open):
+    c = rqc.random_circuit(rqc.rect_layout(3, 4), 8, seed=7)
+    open_q, fixed_q, bits = _random_split(12, n_open, 100 + n_open)
+    psi = sv.simulate_numpy(c)
+    ref = sv.amplitudes_from_state(psi, 12, open_q, fixed_q, bits)
+    got = nw.amplitudes(c, open_q, fixed_q, bits)
+    np.testing.assert_allclose(got, ref, atol=1e-13)
+    if n_open == 12:
+        np.testing.assert_allclose(got, psi, atol=1e-13)   # all open = full state
+
+
+def test_network_c1_workload():
+    w = rqc.workload("c1_tiny_3x4_m8")
+    psi = sv.simulate_numpy(w["circuit"])
+    ref = sv.amplitudes_from_state(psi, 12, w["open_q"], w["fixed_q"], w["bits"])
+    got = nw.amplitudes(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    np.testing.assert_allclose(got, ref, atol=1e-13)
+
+
+def test_qubit_without_two_qubit_gates():
+    # a 1x3 line with one cycle of pattern A touches qubits 0,1 only
+    c = rqc.random_circuit(rqc.rect_layout(1, 3), 1, seed=1)
+    assert all(2 not in g.qubits for g in c.two_qubit_gates())
+    psi = sv.simulate_numpy(c)
+    for open_q in ([0, 2], [2], [1]):
+        fixed_q = [q for q in range(3) if q not in open_q]
+        bits = np.ones(len(fixed_q), dtype=np.uint8)
+        ref = sv.amplitudes_from_state(psi, 3, open_q, fixed_q, bits)
+        np.testing.assert_allclose(nw.amplitudes(c, open_q, fixed_q, bits), ref, atol=1e-14)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 4])
+def test_slicing_sum_is_exact(k):
+    w = rqc.workload("c1_tiny_3x4_m8")
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    rng = np.random.default_rng(k)
+    edges = net.internal_edges()
+    sliced = [edges[i] for i in sorted(rng.choice(len(edges), size=k, replace=False))]
+    full = nw.contract(net)
+    parts = nw.amplitudes(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], sliced=sliced)
+    np.testing.assert_allclose(parts, full, atol=1e-13)
+    if k:
+        with pytest.raises(ValueError):
+            nw.slice_network(net, [net.open_labels[0]], [0])
+
+
+def test_slice_values_order_invariant():
+    w = rqc.workload("c1_tiny_3x4_m8")
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    sliced = net.internal_edges()[20:23]
+    for j in (0, 5, 7):
+        sub = nw.slice_network(net, sliced, nw.slice_values(sliced, j))
+        a = nw.contract(sub, nw.greedy_order(sub.labels))
+        b = nw.contract(sub, nw.random_order(sub.labels, seed=j))
+        np.testing.assert_allclose(a, b, atol=1e-13)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_product_circuit_closed_form(seed):
+    c = rqc.product_circuit(rqc.rect_layout(3, 4), 8, seed=seed)
+    open_q, fixed_q, bits = _random_split(12, 5, seed)
+    psi = sv.simulate_numpy(c)
+    ref = sv.amplitudes_from_state(psi, 12, open_q, fixed_q, bits)
+    np.testing.assert_allclose(cf.product_amplitudes(c, open_q, fixed_q, bits), ref, atol=1e-14)
+    net = nw.build_network(c, open_q, fixed_q, bits)
+    rng = np.random.default_rng(seed)
+    edges = net.internal_edges()
+    sliced = [edges[i] for i in sorted(rng.choice(len(edges), size=4, replace=False))]
+    for j in range(16):
+        np.testing.assert_allclose(nw.slice_amplitudes(net, sliced, j),
+                                   cf.product_amplitudes(c, open_q, fixed_q, bits, sliced, j),
+                                   atol=1e-14)
+
+
+def test_product_closed_form_rejects_entangling_gate():
+    with pytest.raises(ValueError):
+        cf.factor_product_gate(G.fsim(np.pi / 2, np.pi / 6))
+
+
+# --- statistics -----------------------------------------------------------
+
+def test_xeb_identities():
+    rng = np.random.default_rng(0)
+    n, n2 = 20, 10
+    p_uniform = np.full(1 << n2, 2.0 ** -n)
+    assert abs(stats.xeb(p_uniform, n)) < 1e-12
+    a = (rng.normal(size=1 << n2) + 1j * rng.normal(size=1 << n2)) * 2.0 ** (-n / 2) / np.sqrt(2)
+    p = stats.probabilities(a)
+    f = stats.xeb(p, n)
+    assert np.isclose(stats.marginal(p), (f + 1) * 2.0 ** -(n - n2), rtol=1e-12)
+    q = stats.conditional(p)
+    assert abs(stats.xeb(q, n2)) < 1e-12                      # exactly 0 up to rounding
+    np.testing.assert_allclose(stats.topk_curve(p, n, [p.size])[0], f, rtol=1e-12)
+    top1 = stats.topk_curve(p, n, [1])[0]
+    assert np.isclose(top1, 2.0 ** n * p.max() - 1)
+
+
+@pytest.mark.slow
+def test_porter_thomas_on_25_qubit_state(c2_state):
+    _, psi = c2_state
+    assert abs(np.linalg.norm(psi) - 1) < 1e-12
+    p = stats.probabilities(psi)
+    assert abs(stats.xeb_self(p, 25) - 1.0) < 0.02
+    assert abs(stats.pt_second_moment(p, 25) - 2.0) < 0.04
+    assert stats.pt_ks_distance(p, 25) < 0.01
+
+
+def test_efficiency_eq3_reproduces_paper():
+    g = _golden()["efficiency_eq3"]
+    for case in g["cases"]:
+        e = stats.efficiency(case["complex_macs"], case["peak_flops"], case["seconds"])
+        assert abs(e - case["efficiency"]) < g["abs_tol"], case["gpu"]
+
+
+def test_table_iii_probability_is_amplitude_squared():
+    g = _golden()["table_iii"]
+    for row in g["rows"]:
+        p = stats.probabilities(np.array([row["amplitude"]]))[0]
+        assert abs(p - row["probability"]) / row["probability"] < g["rel_tol"]
+
+
+def test_table_i_and_days_accounting():
+    g = _golden()
+    t = g["table_i"]
+    assert abs(2 ** t["log2_subtasks"] * t["t_sub"] / t["t_head"] - 1) < t["rel_tol_head"]
+    assert abs(2 ** t["log2_amplitudes"] * t["t_tail_per_s2"] / t["t_tail"] - 1) < t["rel_tol_tail"]
+    d = g["one_gpu_days"]
+    days = 2 ** d["log2_subtasks"] * d["seconds_per_subtask"] / 86400.0
+    assert abs(days - d["days"]) < d["abs_tol_days"]
+
+
+def test_pairwise_cost_model():
+    # Fig. 3: contracting A and B costs 2^(nA + nB + nAB) for bond dimension 2
+    labels = [[(0, 0), (0, 1), (1, 0)], [(1, 0), (2, 0)]]      # nA = 2, nAB = 1, nB = 1
+    mx, macs = nw.log2_sizes(labels, [(0, 1)])
+    assert macs == 2 ** (2 + 1 + 1) and mx == 3
+
+
+# --- learned-model reference ---------------------------------------------
+
+def test_mlp_gradient_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    p = mlp.init_params(6, hidden=16, seed=1)
+    x = rng.normal(size=(32, 6))
+    t = rng.normal(size=32)
+    g = mlp.backward(p, x, t)
+    for key in p:
+        for _ in range(3):
+            idx = tuple(int(rng.integers(s)) for s in p[key].shape)
+            fd = mlp.finite_difference(p, x, t, key, idx)
+            assert abs(fd - g[key][idx]) <= 1e-6 * max(1.0, abs(fd)), key
+
+
+def test_mlp_linear_closed_form():
+    # with all pre-activations positive the network is linear:
+    # y = ((x W1 + b1) W2 + b2) W3 + b3
+    p = mlp.init_params(3, hidden=4, seed=2)
+    for k in ("w1", "w2", "w3"):
+        p[k] = np.abs(p[k])
+    p["b1"][:] = 5.0
+    p["b2"][:] = 5.0
+    x = np.abs(np.random.default_rng(3).normal(size=(5, 3)))
+    y, _ = mlp.forward(p, x)
+    lin = ((x @ p["w1"] + 5.0) @ p["w2"] + 5.0) @ p["w3"] + p["b3"]
+    np.testing.assert_allclose(y, lin[:, 0], rtol=1e-14)
+
+
+def test_adam_first_step_is_signed_lr():
+    # Adam's first bias-corrected step is -lr * g / (|g| + eps) elementwise
+    p = {"w": np.array([1.0, -2.0, 3.0])}
+    g = {"w": np.array([0.5, -4.0, 1e-3])}
+    mlp.adam_step(p, g, {}, lr=0.1, eps=0.0)
+    np.testing.assert_allclose(p["w"], [0.9, -1.9, 2.9], rtol=1e-14)
