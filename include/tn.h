@@ -1,0 +1,213 @@
+/*
+ * tn.h -- C ABI of the sliced big-head tensor-network contraction on MI355X.
+ *
+ * The library computes, for a random quantum circuit U on n qubits, the
+ * amplitudes of all 2^n2 bitstrings that agree with fixed bits s1 on the n1
+ * closed qubits and take every value on the n2 open qubits:
+ *
+ *     A[s2] = <s1; s2| U |0^n>,
+ *
+ * by contracting the circuit's tensor network (single-qubit gates absorbed
+ * into two-qubit gates; section "Computing bitstring probabilities"), sliced
+ * into 2^k independent subtasks whose results are summed (appendix A,
+ * "Dynamic slicing"), with the big-head split of the network into a head of
+ * closed qubits and a tail of open qubits joined by a small cut (section
+ * "Big-head simulation of quantum circuits").  XEB (Eq. 1) and the marginal
+ * and conditional probabilities (appendix C) are computed from the result.
+ *
+ * Conventions shared by every call:
+ *  - Every function returns tn_status: 0 on success, a negative code on
+ *    failure; tn_last_error() then returns a thread-local message.  No call
+ *    aborts the process or lets a C++ exception escape.
+ *  - Complex numbers are interleaved (re, im).  Device buffers named d_* are
+ *    device pointers allocated by the caller (e.g. through PyTorch) on the
+ *    current HIP device; h_* are host pointers owned by the caller.
+ *  - Calls taking a hip_stream (a hipStream_t, NULL = the null stream) are
+ *    asynchronous on that stream unless stated otherwise.
+ *  - Qubit q is bit (n-1-q) of a full basis index; the amplitude index of
+ *    s2 takes the open qubits in ascending id, the first open qubit as the
+ *    most significant bit.
+ *  - Edge (q, t) is the wire of qubit q after its t-th two-qubit gate
+ *    (t = 0, 1, ...); (q, -1) is the wire of a qubit with no two-qubit gate.
+ *    Single-qubit gates are absorbed forward into the next two-qubit gate on
+ *    their qubit, trailing ones backward into the last, |0> into the first
+ *    and the projector <s1_q| into the last two-qubit gate of qubit q.
+ *  - Slice j fixes the i-th sliced edge to bit i of j.
+ */
+#ifndef TN_H
+#define TN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tn_plan_s* tn_plan_t;
+
+typedef enum {
+    TN_OK = 0,
+    TN_EINVAL = -1,        /* bad argument (see each call) */
+    TN_ENOMEM = -2,        /* host or device allocation failed */
+    TN_EDEVICE = -3,       /* a HIP call failed */
+    TN_ESTATE = -4,        /* call made in a state that does not allow it */
+    TN_EUNSUPPORTED = -5   /* option with no implementation */
+} tn_status;
+
+typedef enum {
+    TN_C64 = 0,        /* complex64 storage, FP32 MFMA (the paper's precision) */
+    TN_C128 = 1,       /* complex128 storage and arithmetic (FP64 recontraction) */
+    TN_SPLIT_FP16 = 2, /* complex64 storage, products as hi/lo FP16 pairs on FP16 MFMA,
+                          FP32 accumulation, per-tensor power-of-two scaling */
+    TN_BF16 = 3        /* BF16 complex storage, BF16 MFMA, FP32 accumulation */
+} tn_precision;
+
+/* One gate: q1 = -1 for a single-qubit gate.  Matrix row-major, row = output
+ * basis state, column = input; two-qubit basis |q0 q1> with q0 the more
+ * significant bit.  2x2 gates use the first 4 entries. */
+typedef struct {
+    int32_t q0, q1;
+    double re[16], im[16];
+} tn_gate;
+
+/* A circuit: gates in time order, initial state |0^n>. */
+typedef struct {
+    int32_t n_qubits;
+    int32_t n_gates;
+    const tn_gate* gates;
+} tn_circuit;
+
+typedef struct {
+    int32_t qubit, segment;   /* edge (q, t) */
+} tn_edge;
+
+/* A contraction tree as SSA pairs: leaves are 0..L-1 in network order (one
+ * per two-qubit gate in time order, then one per gate-less qubit in id
+ * order); step s creates node L+s from nodes lhs[s] and rhs[s]. */
+typedef struct {
+    int32_t n_steps;
+    const int32_t* lhs;
+    const int32_t* rhs;
+} tn_tree;
+
+typedef struct {
+    tn_precision prec;
+    int32_t max_log2_size;   /* memory target: largest intermediate of one slice
+                                (log2 elements); slicing continues until met */
+    int32_t n_slice_edges;   /* >= 0: slice at least this many edges; -1: target only */
+    int32_t batch_log2;      /* slices contracted together per launch sequence
+                                (log2); -1 = chosen by the planner */
+    int32_t branch_merge;    /* 1 = merge small branches before large steps */
+    int32_t bighead;         /* 1 = head/tail split with the head summed over slices
+                                and the tail applied once; 0 = single tree */
+    int32_t restarts;        /* randomised greedy trees tried (>= 1) */
+    int32_t cost_model;      /* 0 = FLOP/byte roofline model, 1 = learned MLP */
+    uint64_t seed;
+    int64_t max_workspace_bytes;  /* cap for the per-launch workspace (0 = 32 GiB) */
+} tn_plan_opts;
+
+typedef struct {
+    uint64_t n_slices;            /* 2^n_sliced */
+    int32_t n_sliced;             /* sliced edges */
+    int32_t batch_log2;           /* slices per launch sequence (log2) */
+    int32_t n_open, n_leaves, n_steps;
+    int32_t n_c;                  /* cut legs between head and tail (bighead), else 0 */
+    int32_t max_log2_size;        /* largest intermediate of one slice (log2 elements) */
+    int32_t acc_log2;             /* accumulator length = 2^acc_log2 complex128 */
+    double cmacs_per_slice;       /* complex multiply-adds per slice, executed tree */
+    double cmacs_per_slice_unmerged; /* same before branch merging */
+    double cmacs_invariant;       /* slice-invariant work done once per plan */
+    double cmacs_tail;            /* tail / amplitude work done once per run */
+    double bytes_per_slice;       /* algorithmic HBM bytes per slice (operands + results) */
+    double cmacs_per_batch;       /* complex multiply-adds per launch sequence */
+    double bytes_per_batch;
+    uint64_t workspace_bytes;     /* minimum ws_bytes for tn_contract_slices */
+    uint64_t tail_workspace_bytes;/* minimum ws_bytes for tn_amplitudes */
+    int32_t n_dense_steps;        /* steps run on MFMA tiles */
+    int32_t n_small_steps;        /* steps run on the streaming VALU kernel */
+} tn_plan_stats;
+
+typedef struct {
+    double F_unif;     /* Eq. (1) over all 2^n2 amplitudes, equal weights */
+    double F_self;     /* 2^n * sum P^2 / sum P - 1 */
+    double P_s1;       /* marginal probability sum_s2 P(s1; s2) */
+    double cond_xeb;   /* XEB of P(s2|s1) over the open qubits (0 up to rounding) */
+    double p_max, p_min;
+} tn_xeb_result;
+
+/* Build a plan (host only; no device work).  Section "The algorithm" and
+ * appendix A: contraction order (randomised greedy, or the caller's tree),
+ * slicing to the memory target, slice-invariant subtrees hoisted, big-head
+ * split, branch merging, per-step layouts.
+ *   c              circuit (copied)
+ *   open_q/fixed_q disjoint, together every qubit exactly once
+ *   fixed_bits     s1, one byte (0/1) per fixed qubit, in fixed_q order
+ *   tree           NULL = planner's order; else SSA pairs over the leaves
+ *   sliced         NULL with n_sliced = -1: planner chooses; else the edges to
+ *                  slice (must be internal edges, not open legs)
+ *   opts           NULL = defaults (C64, target 2^30, planner batching)
+ * Errors: TN_EINVAL for a bad circuit, overlapping or missing qubits, a bad
+ * tree or edge; TN_ENOMEM.  On success *out owns every input it needs. */
+tn_status tn_plan(const tn_circuit* c,
+                  const int32_t* open_q, int32_t n_open,
+                  const int32_t* fixed_q, const uint8_t* fixed_bits, int32_t n_fixed,
+                  const tn_tree* tree, const tn_edge* sliced, int32_t n_sliced,
+                  const tn_plan_opts* opts, tn_plan_t* out);
+
+/* Statistics of a plan (host only). */
+tn_status tn_plan_stats_get(tn_plan_t p, tn_plan_stats* out);
+
+/* The sliced edges in slice-bit order; *n receives the count (<= cap are
+ * written). */
+tn_status tn_plan_sliced_edges(tn_plan_t p, tn_edge* out, int32_t cap, int32_t* n);
+
+/* JSON description of the plan (tree, leaves' edge names, sliced and batch
+ * edges, per-step shapes, costs and kernel choices).  Writes at most cap
+ * bytes including the terminating NUL; *need receives the full size. */
+tn_status tn_plan_export_json(tn_plan_t p, char* buf, size_t cap, size_t* need);
+
+/* Contract slices [slice_begin, slice_end) and add their sum, in float64, to
+ * the accumulator d_acc (2^acc_log2 complex128, caller-zeroed before the
+ * first call).  Sums over disjoint ranges add up to the sum over their
+ * union.  d_workspace must hold stats.workspace_bytes.  The first call on a
+ * device uploads the plan's leaves and computes its slice-invariant
+ * subtrees.  Errors: TN_EINVAL (range, sizes, NULL), TN_EDEVICE. */
+tn_status tn_contract_slices(tn_plan_t p, void* d_workspace, size_t ws_bytes,
+                             double* d_acc, uint64_t slice_begin, uint64_t slice_end,
+                             void* hip_stream);
+
+/* Same for an explicit host list of slice ids (each < n_slices). */
+tn_status tn_contract_slice_list(tn_plan_t p, void* d_workspace, size_t ws_bytes,
+                                 double* d_acc, const uint64_t* h_slice_ids, uint64_t n_ids,
+                                 void* hip_stream);
+
+/* Turn the accumulator into the 2^n_open amplitudes d_amps (complex128):
+ * with the big-head split this contracts the tail with the summed head
+ * vector (section "Big-head simulation", the final inner product
+ * v_head . v_tail(s2)); without it the accumulator already holds A and is
+ * copied.  d_workspace must hold stats.tail_workspace_bytes. */
+tn_status tn_amplitudes(tn_plan_t p, const double* d_acc, double* d_amps,
+                        void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* Statistics of d_amps (2^n_open complex128) in float64 on the device:
+ * Eq. (1) with equal weights, F_self, P(s1) and the conditional XEB
+ * (appendix C).  `weight` multiplies every probability first (1 for full
+ * amplitudes; 2^k / |S| for partial sums over a sample S of slices).  If
+ * n_ks > 0, h_topk[i] receives the XEB of the ks[i] largest probabilities
+ * (post-selection curve of section "Fidelity").  Synchronises the stream. */
+tn_status tn_xeb(const double* d_amps, int32_t n_open, int32_t n_qubits, double weight,
+                 const int64_t* ks, int32_t n_ks, double* h_topk,
+                 tn_xeb_result* out, void* hip_stream);
+
+/* Release a plan and its device memory (NULL is ignored). */
+void tn_plan_destroy(tn_plan_t p);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* tn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TN_H */

@@ -1,0 +1,270 @@
+// extern "C" entry points declared in include/tn.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "exec.hpp"
+#include "plan.hpp"
+
+struct tn_plan_s {
+    tn::Plan plan;
+    tn::DeviceState dev;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+tn_status fail(tn_status s, const std::string& m) {
+    g_err = m;
+    return s;
+}
+
+tn_status from_err(const std::string& e) {
+    if (e.empty()) return TN_OK;
+    return fail(TN_EDEVICE, e);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tn_last_error(void) { return g_err.c_str(); }
+
+tn_status tn_plan(const tn_circuit* c, const int32_t* open_q, int32_t n_open, const int32_t* fixed_q,
+                  const uint8_t* fixed_bits, int32_t n_fixed, const tn_tree* tree, const tn_edge* sliced,
+                  int32_t n_sliced, const tn_plan_opts* opts, tn_plan_t* out) {
+    if (!out) return fail(TN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c) return fail(TN_EINVAL, "circuit is NULL");
+    if (n_open < 0 || n_fixed < 0 || (n_open > 0 && !open_q) || (n_fixed > 0 && (!fixed_q || !fixed_bits)))
+        return fail(TN_EINVAL, "bad open/fixed qubit arrays");
+    if (n_sliced > 0 && !sliced) return fail(TN_EINVAL, "sliced is NULL");
+    if (tree && tree->n_steps > 0 && (!tree->lhs || !tree->rhs)) return fail(TN_EINVAL, "bad tree arrays");
+    if (n_open > 40) return fail(TN_EUNSUPPORTED, "more than 40 open qubits");
+    try {
+        std::vector<int> o(open_q, open_q + n_open), f(fixed_q, fixed_q + n_fixed);
+        std::vector<uint8_t> b(fixed_bits, fixed_bits + n_fixed);
+        tn_plan_opts op = opts ? *opts : tn::default_opts();
+        if (op.prec == TN_BF16 || op.prec == TN_SPLIT_FP16)
+            return fail(TN_EUNSUPPORTED, "precision not available in this build");
+        auto* h = new tn_plan_s;
+        std::string err = tn::make_plan(*c, o, f, b, tree, sliced, n_sliced, op, h->plan);
+        if (!err.empty()) {
+            delete h;
+            return fail(TN_EINVAL, err);
+        }
+        *out = h;
+        return TN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(TN_ENOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(TN_EINVAL, e.what());
+    }
+}
+
+tn_status tn_plan_stats_get(tn_plan_t p, tn_plan_stats* out) {
+    if (!p || !out) return fail(TN_EINVAL, "NULL argument");
+    *out = p->plan.stats;
+    return TN_OK;
+}
+
+tn_status tn_plan_sliced_edges(tn_plan_t p, tn_edge* out, int32_t cap, int32_t* n) {
+    if (!p || !n || (cap > 0 && !out)) return fail(TN_EINVAL, "NULL argument");
+    const auto& s = p->plan.sliced;
+    *n = (int32_t)s.size();
+    for (int32_t i = 0; i < cap && i < (int32_t)s.size(); ++i) {
+        out[i].qubit = p->plan.net.edge_name[s[i]].q;
+        out[i].segment = p->plan.net.edge_name[s[i]].t;
+    }
+    return TN_OK;
+}
+
+tn_status tn_plan_export_json(tn_plan_t p, char* buf, size_t cap, size_t* need) {
+    if (!p || !need) return fail(TN_EINVAL, "NULL argument");
+    try {
+        std::string j = tn::plan_to_json(p->plan);
+        *need = j.size() + 1;
+        if (buf && cap > 0) {
+            size_t n = std::min(cap - 1, j.size());
+            std::memcpy(buf, j.data(), n);
+            buf[n] = 0;
+        }
+        return TN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(TN_ENOMEM, "host allocation failed");
+    }
+}
+
+static tn_status contract_groups(tn_plan_t p, void* ws, size_t ws_bytes, double* acc,
+                                 const std::vector<tn::Group>& groups, void* stream) {
+    if (!ws || !acc) return fail(TN_EINVAL, "NULL device buffer");
+    if (ws_bytes < p->plan.stats.workspace_bytes)
+        return fail(TN_EINVAL, "workspace too small: need " + std::to_string(p->plan.stats.workspace_bytes));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    try {
+        std::string e = tn::prepare(p->plan, p->dev, s);
+        if (!e.empty()) return fail(TN_EDEVICE, e);
+        return from_err(tn::run_groups(p->plan, p->dev, ws, acc, groups, s));
+    } catch (const std::bad_alloc&) {
+        return fail(TN_ENOMEM, "host allocation failed");
+    }
+}
+
+tn_status tn_contract_slices(tn_plan_t p, void* d_workspace, size_t ws_bytes, double* d_acc, uint64_t slice_begin,
+                             uint64_t slice_end, void* hip_stream) {
+    if (!p) return fail(TN_EINVAL, "plan is NULL");
+    const uint64_t n = p->plan.stats.n_slices;
+    if (slice_begin > slice_end || slice_end > n) return fail(TN_EINVAL, "slice range out of bounds");
+    if (slice_begin == slice_end) return TN_OK;
+    const int b = p->plan.batch_log2;
+    const uint64_t B = 1ull << b;
+    std::vector<tn::Group> groups;
+    for (uint64_t o = slice_begin >> b; o <= (slice_end - 1) >> b; ++o) {
+        tn::Group g;
+        g.slice_base = o << b;
+        g.beta0 = (o == (slice_begin >> b)) ? (slice_begin & (B - 1)) : 0;
+        g.beta1 = (o == ((slice_end - 1) >> b)) ? ((slice_end - 1) & (B - 1)) + 1 : B;
+        groups.push_back(g);
+    }
+    return contract_groups(p, d_workspace, ws_bytes, d_acc, groups, hip_stream);
+}
+
+tn_status tn_contract_slice_list(tn_plan_t p, void* d_workspace, size_t ws_bytes, double* d_acc,
+                                 const uint64_t* h_slice_ids, uint64_t n_ids, void* hip_stream) {
+    if (!p) return fail(TN_EINVAL, "plan is NULL");
+    if (n_ids == 0) return TN_OK;
+    if (!h_slice_ids) return fail(TN_EINVAL, "slice id list is NULL");
+    const uint64_t n = p->plan.stats.n_slices;
+    const int b = p->plan.batch_log2;
+    const uint64_t B = 1ull << b;
+    std::vector<uint64_t> ids(h_slice_ids, h_slice_ids + n_ids);
+    std::sort(ids.begin(), ids.end());
+    for (size_t i = 0; i < ids.size(); ++i) {
+        if (ids[i] >= n) return fail(TN_EINVAL, "slice id out of range");
+        if (i && ids[i] == ids[i - 1]) return fail(TN_EINVAL, "slice id repeated");
+    }
+    std::vector<tn::Group> groups;
+    const size_t words = std::max<size_t>(1, (B + 31) / 32);
+    for (size_t i = 0; i < ids.size();) {
+        const uint64_t o = ids[i] >> b;
+        tn::Group g;
+        g.slice_base = o << b;
+        g.mask.assign(words, 0);
+        size_t cnt = 0;
+        while (i < ids.size() && (ids[i] >> b) == o) {
+            const uint64_t be = ids[i] & (B - 1);
+            g.mask[be >> 5] |= 1u << (be & 31);
+            ++i;
+            ++cnt;
+        }
+        if (cnt == B) {   // full group: plain range
+            g.mask.clear();
+            g.beta0 = 0;
+            g.beta1 = B;
+        }
+        groups.push_back(std::move(g));
+    }
+    return contract_groups(p, d_workspace, ws_bytes, d_acc, groups, hip_stream);
+}
+
+tn_status tn_amplitudes(tn_plan_t p, const double* d_acc, double* d_amps, void* d_workspace, size_t ws_bytes,
+                        void* hip_stream) {
+    (void)d_workspace;
+    (void)ws_bytes;
+    if (!p || !d_acc || !d_amps) return fail(TN_EINVAL, "NULL argument");
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const uint64_t n = 2ull << p->plan.root_log2;
+    hipError_t e = tn::launch_copy_acc(d_acc, d_amps, n, s);
+    if (e != hipSuccess) return fail(TN_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
+    return TN_OK;
+}
+
+tn_status tn_xeb(const double* d_amps, int32_t n_open, int32_t n_qubits, double weight, const int64_t* ks,
+                 int32_t n_ks, double* h_topk, tn_xeb_result* out, void* hip_stream) {
+    if (!d_amps || !out) return fail(TN_EINVAL, "NULL argument");
+    if (n_open < 0 || n_open > 40 || n_qubits < n_open || n_qubits > 4096) return fail(TN_EINVAL, "bad sizes");
+    if (n_ks < 0 || (n_ks > 0 && (!ks || !h_topk))) return fail(TN_EINVAL, "bad top-k arrays");
+    if (!(weight > 0)) return fail(TN_EINVAL, "weight must be positive");
+    const uint64_t L = 1ull << n_open;
+    for (int i = 0; i < n_ks; ++i)
+        if (ks[i] < 1 || (uint64_t)ks[i] > L) return fail(TN_EINVAL, "top-k size out of range");
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const int blocks = (int)std::min<uint64_t>(1024, (L + 255) / 256);
+    double* part = nullptr;
+    hipError_t e = hipMallocAsync((void**)&part, sizeof(double) * 5 * blocks, s);
+    if (e != hipSuccess) return fail(TN_EDEVICE, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    std::vector<double> h(5 * blocks);
+    auto done = [&](tn_status st) {
+        (void)hipFreeAsync(part, s);
+        (void)hipStreamSynchronize(s);
+        return st;
+    };
+    if ((e = tn::launch_xeb_partials(d_amps, L, weight, part, blocks, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(h.data(), part, sizeof(double) * 4 * blocks, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return done(fail(TN_EDEVICE, std::string("xeb: ") + hipGetErrorString(e)));
+    double s1 = 0, s2 = 0, mx = 0, mn = 1e300;
+    for (int b = 0; b < blocks; ++b) {
+        s1 += h[4 * b];
+        s2 += h[4 * b + 1];
+        mx = std::max(mx, h[4 * b + 2]);
+        mn = std::min(mn, h[4 * b + 3]);
+    }
+    if ((e = tn::launch_xeb_cond(d_amps, L, weight, s1 > 0 ? 1.0 / s1 : 0.0, part + 4 * blocks, blocks, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(h.data() + 4 * blocks, part + 4 * blocks, sizeof(double) * blocks, hipMemcpyDeviceToHost,
+                            s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return done(fail(TN_EDEVICE, std::string("xeb: ") + hipGetErrorString(e)));
+    double cs = 0;
+    for (int b = 0; b < blocks; ++b) cs += h[4 * blocks + b];
+    const double two_n = std::ldexp(1.0, n_qubits);
+    out->P_s1 = s1;
+    out->F_unif = two_n / (double)L * s1 - 1.0;
+    out->F_self = s1 > 0 ? two_n * s2 / s1 - 1.0 : -1.0;
+    out->cond_xeb = cs - 1.0;   // 2^n2 / L * sum P(s2|s1) - 1 with L = 2^n2
+    out->p_max = mx;
+    out->p_min = mn;
+    if (n_ks > 0) {
+        std::vector<double> a(2 * L);
+        if ((e = hipMemcpyAsync(a.data(), d_amps, sizeof(double) * 2 * L, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return done(fail(TN_EDEVICE, std::string("xeb copy: ") + hipGetErrorString(e)));
+        std::vector<double> pr(L);
+        for (uint64_t i = 0; i < L; ++i) pr[i] = weight * (a[2 * i] * a[2 * i] + a[2 * i + 1] * a[2 * i + 1]);
+        std::sort(pr.begin(), pr.end(), [](double x, double y) { return x > y; });
+        std::vector<int64_t> order(n_ks);
+        for (int i = 0; i < n_ks; ++i) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return ks[x] < ks[y]; });
+        double c = 0;
+        uint64_t pos = 0;
+        for (int64_t oi : order) {
+            while (pos < (uint64_t)ks[oi]) c += pr[pos++];
+            h_topk[oi] = two_n / (double)ks[oi] * c - 1.0;
+        }
+    }
+    return done(TN_OK);
+}
+
+void tn_plan_destroy(tn_plan_t p) {
+    if (!p) return;
+    if (p->dev.prepared || p->dev.plan_mem) {
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess && p->dev.device >= 0 && cur != p->dev.device) {
+            (void)hipSetDevice(p->dev.device);
+            tn::release(p->dev);
+            (void)hipSetDevice(cur);
+        } else {
+            tn::release(p->dev);
+        }
+    }
+    delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,37 @@
+// Executor: runs a plan's steps on one HIP stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace tn {
+
+struct DeviceState {
+    int device = -1;
+    void* plan_mem = nullptr;     // leaves + slice-invariant tensors
+    size_t plan_bytes = 0;
+    bool prepared = false;
+    uint32_t* d_mask = nullptr;   // batch-slot masks for slice lists
+    size_t mask_words = 0;
+    double* d_part = nullptr;     // XEB partials
+};
+
+struct Group {
+    uint64_t slice_base;          // slice id with the batch bits zero
+    uint64_t beta0, beta1;        // batch slots [beta0, beta1) when mask is empty
+    std::vector<uint32_t> mask;   // explicit batch slots (slice lists)
+};
+
+std::string prepare(Plan& p, DeviceState& d, hipStream_t s);
+std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std::vector<Group>& groups,
+                       hipStream_t s);
+void release(DeviceState& d);
+
+int storage_of(tn_precision p);
+
+}  // namespace tn

@@ -1,0 +1,452 @@
+// Step kernels for gfx950 (CDNA4).
+//
+// One pairwise contraction step of the sliced network (appendix A, Fig. 3:
+// cost 2^(nA + nB + nAB) for bond dimension 2) is
+//     C[b, m, n] = sum_k A[k, b, m] * B[k, b, n]
+// over complex numbers.  The planner lays every operand out as
+// [K | batch | M] (resp. N) from the most to the least significant address
+// bit, so A and B tiles are plain strided rows, and C goes to whatever
+// address bits its consumer wants: the output tile is staged in LDS and
+// written back in C-address order, which is where the index permutation of
+// each step happens (no separate permute pass).
+//
+// Kernels:
+//  k_valu        streaming VALU tile kernel (big-times-small steps, any shape)
+//  k_splitk_red  sum of split-K partial tiles in fixed order
+//  k_mfma_c64    complex GEMM on FP32 MFMA (v_mfma_f32_16x16x4f32): each
+//                complex product is 4 real products; B is expanded on the fly
+//                into the 2x2 real block [[re, im], [-im, re]]
+//  k_slice_sum   float64 sum over the batch legs of the root into the
+//                accumulator (fixed order, no atomics)
+//  k_xeb_*       float64 block partials of sum P, sum P^2, max, min
+#include "kernels.hpp"
+
+namespace tn {
+
+namespace {
+
+__device__ __forceinline__ float2 cfma(float2 acc, float2 a, float2 b) {
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(-a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(a.y, b.x, acc.y);
+    return acc;
+}
+__device__ __forceinline__ double2 cfma(double2 acc, double2 a, double2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+template <typename T> __device__ __forceinline__ T czero();
+template <> __device__ __forceinline__ float2 czero<float2>() { return make_float2(0.f, 0.f); }
+template <> __device__ __forceinline__ double2 czero<double2>() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// Scatter the bits [lo, hi) of x to the address bits pos[lo..hi).
+__device__ __forceinline__ uint64_t deposit(uint64_t x, const uint8_t* pos, int lo, int hi) {
+    uint64_t r = 0;
+    for (int i = lo; i < hi; ++i) r |= ((x >> i) & 1ull) << pos[i];
+    return r;
+}
+
+struct TileIndex {
+    uint64_t m0, n0, beta, split;
+};
+
+__device__ __forceinline__ TileIndex tile_index(const GemmArgs& g) {
+    uint64_t t = blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+    const int mtb = g.m_log - g.tm, ntb = g.n_log - g.tn;
+    TileIndex ti;
+    ti.m0 = (t & ((1ull << mtb) - 1)) << g.tm;
+    t >>= mtb;
+    ti.n0 = (t & ((1ull << ntb) - 1)) << g.tn;
+    t >>= ntb;
+    ti.beta = t & ((1ull << g.b_log) - 1);
+    t >>= g.b_log;
+    ti.split = t;
+    return ti;
+}
+
+// Decode tile element x (enumerated in C-address order) into its logical
+// (m, n) position in the tile and its address offset.
+__device__ __forceinline__ uint64_t decode_ep(const GemmArgs& g, int x, int& ml, int& nl) {
+    uint64_t off = 0;
+    ml = 0;
+    nl = 0;
+    for (int i = 0; i < g.ep_n; ++i) {
+        const int bit = (x >> i) & 1;
+        off |= (uint64_t)bit << g.ep_pos[i];
+        const int s = g.ep_src[i];
+        if (s < 32) ml |= bit << s;
+        else nl |= bit << (s - 32);
+    }
+    return off;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ VALU
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_valu(GemmArgs g) {
+    extern __shared__ unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const int TM = 1 << g.tm, TN = 1 << g.tn, TK = 1 << g.tk;
+    T* As = sm;
+    T* Bs = sm + (TK << g.tm);
+    const TileIndex ti = tile_index(g);
+    const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
+    const T* A = reinterpret_cast<const T*>(g.A) + (ti.beta << g.m_log) + ti.m0;
+    const T* B = reinterpret_cast<const T*>(g.B) + (ti.beta << g.n_log) + ti.n0;
+    const int kc_log = g.k_log - g.split_log;
+    const uint64_t kb = ti.split << kc_log;
+    const uint64_t kn = 1ull << kc_log;
+    const int tid = threadIdx.x;
+    const int ntile = 1 << (g.tm + g.tn);
+    T acc[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc[j] = czero<T>();
+    for (uint64_t k0 = 0; k0 < kn; k0 += TK) {
+        for (int e = tid; e < (TK << g.tm); e += 256) {
+            const int kk = e >> g.tm, mm = e & (TM - 1);
+            As[e] = A[(kb + k0 + kk) * sAk + mm];
+        }
+        for (int e = tid; e < (TK << g.tn); e += 256) {
+            const int kk = e >> g.tn, nn = e & (TN - 1);
+            Bs[e] = B[(kb + k0 + kk) * sBk + nn];
+        }
+        __syncthreads();
+        for (int kk = 0; kk < TK; ++kk) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int o = tid + 256 * j;
+                if (o < ntile) {
+                    const int ml = o & (TM - 1), nl = o >> g.tm;
+                    acc[j] = cfma(acc[j], As[(kk << g.tm) + ml], Bs[(kk << g.tn) + nl]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (g.split_log > 0) {
+        T* P = reinterpret_cast<T*>(g.scratch);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int o = tid + 256 * j;
+            if (o < ntile) {
+                const int ml = o & (TM - 1), nl = o >> g.tm;
+                const uint64_t idx =
+                    ((((ti.split << g.b_log) | ti.beta) << g.n_log | (ti.n0 + nl)) << g.m_log) | (ti.m0 + ml);
+                P[idx] = acc[j];
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int o = tid + 256 * j;
+        if (o < ntile) sm[o] = acc[j];
+    }
+    __syncthreads();
+    const uint64_t cbase = deposit(ti.m0, g.cpm, g.tm, g.m_log) + deposit(ti.n0, g.cpn, g.tn, g.n_log) +
+                           deposit(ti.beta, g.cpb, 0, g.b_log);
+    T* C = reinterpret_cast<T*>(g.C) + cbase;
+    for (int x = tid; x < ntile; x += 256) {
+        int ml, nl;
+        const uint64_t off = decode_ep(g, x, ml, nl);
+        C[off] = sm[ml + (nl << g.tm)];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_splitk_red(GemmArgs g) {
+    const int lt = g.m_log + g.n_log + g.b_log;
+    const uint64_t total = 1ull << lt;
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const T* P = reinterpret_cast<const T*>(g.scratch);
+    T s = czero<T>();
+    for (uint64_t sp = 0; sp < (1ull << g.split_log); ++sp) s = cadd(s, P[(sp << lt) + i]);
+    const uint64_t m = i & ((1ull << g.m_log) - 1);
+    const uint64_t n = (i >> g.m_log) & ((1ull << g.n_log) - 1);
+    const uint64_t be = i >> (g.m_log + g.n_log);
+    const uint64_t off = deposit(m, g.cpm, 0, g.m_log) + deposit(n, g.cpn, 0, g.n_log) + deposit(be, g.cpb, 0, g.b_log);
+    reinterpret_cast<T*>(g.C)[off] = s;
+}
+
+// ------------------------------------------------------------------ MFMA
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaSmemFloats = 8192;   // 32 KiB: A/B chunk tiles, then C staging
+
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+__global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
+    constexpr int TM = WAVES_M * WM * 16;   // complex rows
+    constexpr int TNR = WAVES_N * WN * 16;  // real columns
+    constexpr int TN = TNR / 2;             // complex columns
+    constexpr int TKMAX = (16 * (TM + TN) * 2 <= kMfmaSmemFloats) ? 16 : 8;
+    static_assert(TKMAX * (TM + TN) * 2 <= kMfmaSmemFloats, "tile too large");
+    constexpr int RP = (TM * TNR <= kMfmaSmemFloats) ? TM : kMfmaSmemFloats / TNR;  // rows per epilogue pass
+    __shared__ __attribute__((aligned(16))) float smem[kMfmaSmemFloats];
+    float2* As = reinterpret_cast<float2*>(smem);
+    float2* Bs = As + TKMAX * TM;
+    const TileIndex ti = tile_index(g);
+    const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
+    const float2* A = reinterpret_cast<const float2*>(g.A) + (ti.beta << g.m_log) + ti.m0;
+    const float2* B = reinterpret_cast<const float2*>(g.B) + (ti.beta << g.n_log) + ti.n0;
+    const int TK = 1 << g.tk;
+    const uint64_t K = 1ull << g.k_log;
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, lane = tid & 63;
+    const int wm = w % WAVES_M, wn = w / WAVES_M;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int kc_off = lq >> 1, comp = lq & 1;
+    floatx4 acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (uint64_t k0 = 0; k0 < K; k0 += TK) {
+        for (int e = tid; e < TK * (TM / 2); e += 256) {
+            const int kk = e / (TM / 2), mm = 2 * (e % (TM / 2));
+            const float4 v = *reinterpret_cast<const float4*>(A + (k0 + kk) * sAk + mm);
+            *reinterpret_cast<float4*>(As + kk * TM + mm) = v;
+        }
+        for (int e = tid; e < TK * (TN / 2); e += 256) {
+            const int kk = e / (TN / 2), nn = 2 * (e % (TN / 2));
+            const float4 v = *reinterpret_cast<const float4*>(B + (k0 + kk) * sBk + nn);
+            *reinterpret_cast<float4*>(Bs + kk * TN + nn) = v;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < TK; kk += 2) {
+            const int kc = kk + kc_off;
+            float a[WM], b[WN];
+#pragma unroll
+            for (int bm = 0; bm < WM; ++bm) {
+                const float2 v = As[kc * TM + (wm * WM + bm) * 16 + lr];
+                a[bm] = comp ? v.y : v.x;
+            }
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn) {
+                const int jr = (wn * WN + bn) * 16 + lr;
+                const float2 v = Bs[kc * TN + (jr >> 1)];
+                // real expansion of B: rows (k, re|im), columns (n, re|im)
+                b[bn] = (jr & 1) == 0 ? (comp == 0 ? v.x : -v.y) : (comp == 0 ? v.y : v.x);
+            }
+#pragma unroll
+            for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+                for (int bn = 0; bn < WN; ++bn)
+                    acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bm], b[bn], acc[bm][bn], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // epilogue: stage RP rows at a time, write in C-address order
+    const uint64_t cbase = deposit(ti.m0, g.cpm, g.tm, g.m_log) + deposit(ti.n0, g.cpn, g.tn, g.n_log) +
+                           deposit(ti.beta, g.cpb, 0, g.b_log);
+    float2* C = reinterpret_cast<float2*>(g.C) + cbase;
+    const float2* Cs = reinterpret_cast<const float2*>(smem);
+    for (int p0 = 0; p0 < TM; p0 += RP) {
+#pragma unroll
+        for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = (wm * WM + bm) * 16 + 4 * lq + r;
+                    if (i >= p0 && i < p0 + RP) {
+                        const int jr = (wn * WN + bn) * 16 + lr;
+                        smem[(i - p0) * TNR + jr] = acc[bm][bn][r];
+                    }
+                }
+        __syncthreads();
+        for (int x = tid; x < TM * TN; x += 256) {
+            int ml, nl;
+            const uint64_t off = decode_ep(g, x, ml, nl);
+            if (ml >= p0 && ml < p0 + RP) C[off] = Cs[(ml - p0) * TN + nl];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ slice sum
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_slice_sum(const T* root, double2* acc, int res_log,
+                                                   const uint32_t* mask, uint64_t b0, uint64_t b1) {
+    const uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= (1ull << res_log)) return;
+    double sx = 0.0, sy = 0.0;
+    for (uint64_t be = b0; be < b1; ++be) {
+        if (mask && !((mask[be >> 5] >> (be & 31)) & 1u)) continue;
+        const T v = root[(be << res_log) + r];
+        sx += (double)v.x;
+        sy += (double)v.y;
+    }
+    double2 a = acc[r];
+    a.x += sx;
+    a.y += sy;
+    acc[r] = a;
+}
+
+__global__ void __launch_bounds__(256) k_copy(const double* src, double* dst, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ XEB
+
+__global__ void __launch_bounds__(256) k_xeb_partials(const double2* amps, uint64_t n, double w, double* part) {
+    __shared__ double s1[256], s2[256], smax[256], smin[256];
+    double a = 0, b = 0, mx = 0, mn = 1e300;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const double2 v = amps[i];
+        const double p = w * (v.x * v.x + v.y * v.y);
+        a += p;
+        b += p * p;
+        mx = fmax(mx, p);
+        mn = fmin(mn, p);
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    smax[threadIdx.x] = mx;
+    smin[threadIdx.x] = mn;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            s1[threadIdx.x] += s1[threadIdx.x + h];
+            s2[threadIdx.x] += s2[threadIdx.x + h];
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + h]);
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[4 * blockIdx.x + 0] = s1[0];
+        part[4 * blockIdx.x + 1] = s2[0];
+        part[4 * blockIdx.x + 2] = smax[0];
+        part[4 * blockIdx.x + 3] = smin[0];
+    }
+}
+
+// sum of the conditional probabilities P / P(s1) (appendix C)
+__global__ void __launch_bounds__(256) k_xeb_cond(const double2* amps, uint64_t n, double w, double inv_sum,
+                                                  double* part) {
+    __shared__ double s1[256];
+    double a = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const double2 v = amps[i];
+        a += (w * (v.x * v.x + v.y * v.y)) * inv_sum;
+    }
+    s1[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s1[threadIdx.x] += s1[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s1[0];
+}
+
+// --------------------------------------------------------------- launch
+
+namespace {
+
+dim3 grid_for(uint64_t blocks) {
+    if (blocks <= 0x7fffffffULL) return dim3((unsigned)blocks, 1, 1);
+    unsigned x = 1u << 20;
+    return dim3(x, (unsigned)((blocks + x - 1) / x), 1);
+}
+
+uint64_t tile_blocks(const GemmArgs& g) {
+    return 1ull << ((g.m_log - g.tm) + (g.n_log - g.tn) + g.b_log + g.split_log);
+}
+
+}  // namespace
+
+hipError_t launch_valu(int storage, const GemmArgs& g, int R, hipStream_t s) {
+    const size_t esz = storage == ST_C128 ? 16 : 8;
+    const size_t ab = (size_t)((1 << g.tk) * ((1 << g.tm) + (1 << g.tn)));
+    const size_t st = (size_t)1 << (g.tm + g.tn);
+    const size_t smem = std::max(ab, st) * esz;
+    const dim3 grid = grid_for(tile_blocks(g));
+    if (grid.y > 1 && (uint64_t)grid.x * grid.y != tile_blocks(g)) return hipErrorInvalidValue;
+#define TN_VALU(T, RR) hipLaunchKernelGGL((k_valu<T, RR>), grid, dim3(256), smem, s, g)
+    if (storage == ST_C128) {
+        switch (R) {
+            case 1: TN_VALU(double2, 1); break;
+            case 2: TN_VALU(double2, 2); break;
+            case 4: TN_VALU(double2, 4); break;
+            default: TN_VALU(double2, 8); break;
+        }
+    } else {
+        switch (R) {
+            case 1: TN_VALU(float2, 1); break;
+            case 2: TN_VALU(float2, 2); break;
+            case 4: TN_VALU(float2, 4); break;
+            default: TN_VALU(float2, 8); break;
+        }
+    }
+#undef TN_VALU
+    return hipGetLastError();
+}
+
+hipError_t launch_splitk_reduce(int storage, const GemmArgs& g, hipStream_t s) {
+    const uint64_t total = 1ull << (g.m_log + g.n_log + g.b_log);
+    const dim3 grid = grid_for((total + 255) / 256);
+    if (storage == ST_C128) hipLaunchKernelGGL(k_splitk_red<double2>, grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(k_splitk_red<float2>, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma(int mode, int tile, const GemmArgs& g, hipStream_t s) {
+    (void)mode;
+    const dim3 grid = grid_for(tile_blocks(g));
+    switch (tile) {
+        case 0: hipLaunchKernelGGL((k_mfma_c64<4, 4, 2, 2>), grid, dim3(256), 0, s, g); break;
+        case 1: hipLaunchKernelGGL((k_mfma_c64<2, 2, 2, 2>), grid, dim3(256), 0, s, g); break;
+        case 2: hipLaunchKernelGGL((k_mfma_c64<2, 2, 4, 1>), grid, dim3(256), 0, s, g); break;
+        case 3: hipLaunchKernelGGL((k_mfma_c64<1, 1, 4, 1>), grid, dim3(256), 0, s, g); break;
+        case 4: hipLaunchKernelGGL((k_mfma_c64<4, 1, 4, 1>), grid, dim3(256), 0, s, g); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_sum(int storage, const void* root, double* acc, int res_log, int b_log,
+                            const uint32_t* d_mask, uint64_t beta0, uint64_t beta1, hipStream_t s) {
+    (void)b_log;
+    const uint64_t n = 1ull << res_log;
+    const dim3 grid = grid_for((n + 255) / 256);
+    if (storage == ST_C128)
+        hipLaunchKernelGGL(k_slice_sum<double2>, grid, dim3(256), 0, s, reinterpret_cast<const double2*>(root),
+                           reinterpret_cast<double2*>(acc), res_log, d_mask, beta0, beta1);
+    else
+        hipLaunchKernelGGL(k_slice_sum<float2>, grid, dim3(256), 0, s, reinterpret_cast<const float2*>(root),
+                           reinterpret_cast<double2*>(acc), res_log, d_mask, beta0, beta1);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_acc(const double* src, double* dst, uint64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy, grid_for((n + 255) / 256), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_xeb_partials(const double* amps, uint64_t n, double w, double* part, int blocks,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_xeb_partials, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const double2*>(amps), n,
+                       w, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_xeb_cond(const double* amps, uint64_t n, double w, double inv_sum, double* part, int blocks,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_xeb_cond, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const double2*>(amps), n, w,
+                       inv_sum, part);
+    return hipGetLastError();
+}
+
+}  // namespace tn

@@ -1,0 +1,46 @@
+// Device kernels of the contraction steps (declarations shared with the
+// launcher).  Every step computes C[b, m, n] = sum_k A[k, b, m] * B[k, b, n]
+// over complex numbers, with A and B plain strided arrays and C written to
+// arbitrary address bits (the permutation into the consumer's layout happens
+// while the tile is staged through LDS).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tn {
+
+constexpr int kMaxBits = 40;
+
+struct GemmArgs {
+    const void* A;
+    const void* B;
+    void* C;
+    void* scratch;          // split-K partial tiles
+    int m_log, n_log, k_log, b_log;
+    int tm, tn, tk;         // tile sizes (log2): m, n, k per chunk
+    int split_log;          // K split into 2^split_log parts (partials to scratch)
+    int ep_n;               // number of tile bits in the epilogue decode
+    uint8_t ep_pos[16];     // address bit of the i-th lowest tile bit of C
+    uint8_t ep_src[16];     // logical source: < 32 -> m bit, >= 32 -> n bit (src - 32)
+    uint8_t cpm[kMaxBits], cpn[kMaxBits], cpb[kMaxBits];
+    int scale_a, scale_b;   // power-of-two exponents applied on load (mixed precision)
+    int scale_c;            // exponent applied on store
+};
+
+// storage kinds
+enum Storage : int { ST_C64 = 0, ST_C128 = 1, ST_BF16 = 2 };
+
+hipError_t launch_valu(int storage, const GemmArgs& g, int R, hipStream_t s);
+hipError_t launch_splitk_reduce(int storage, const GemmArgs& g, hipStream_t s);
+hipError_t launch_mfma(int mode, int tile, const GemmArgs& g, hipStream_t s);
+hipError_t launch_slice_sum(int storage, const void* root, double* acc, int res_log, int b_log,
+                            const uint32_t* d_mask, uint64_t beta0, uint64_t beta1, hipStream_t s);
+hipError_t launch_copy_acc(const double* src, double* dst, uint64_t n, hipStream_t s);
+hipError_t launch_xeb_partials(const double* amps, uint64_t n, double w, double* part, int blocks,
+                               hipStream_t s);
+hipError_t launch_xeb_cond(const double* amps, uint64_t n, double w, double inv_sum, double* part,
+                           int blocks, hipStream_t s);
+
+}  // namespace tn

@@ -1,0 +1,761 @@
+// Contraction order, slicing, batching, layouts and the step list (host).
+//
+// Paper passages followed:
+//  - pairwise cost 2^(nA + nB + nAB) for bond dimension 2 (appendix A, Fig. 3);
+//  - greedy contraction order inside sub-graphs (section "The algorithm");
+//  - slicing: fix n_e edges, enumerate the 2^n_e subtasks and sum
+//    (section "The algorithm", appendix A "Dynamic slicing");
+//  - the head/tail split with the head vector reused for every s2
+//    (section "Big-head simulation of quantum circuits").
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <queue>
+#include <random>
+#include <set>
+#include <sstream>
+
+#include "plan.hpp"
+#include "tiles.hpp"
+
+namespace tn {
+
+Legs set_union(const Legs& a, const Legs& b) {
+    Legs r;
+    std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(r));
+    return r;
+}
+Legs set_inter(const Legs& a, const Legs& b) {
+    Legs r;
+    std::set_intersection(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(r));
+    return r;
+}
+Legs set_minus(const Legs& a, const Legs& b) {
+    Legs r;
+    std::set_difference(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(r));
+    return r;
+}
+Legs set_xor(const Legs& a, const Legs& b) {
+    Legs r;
+    std::set_symmetric_difference(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(r));
+    return r;
+}
+
+tn_plan_opts default_opts() {
+    tn_plan_opts o{};
+    o.prec = TN_C64;
+    o.max_log2_size = 30;
+    o.n_slice_edges = -1;
+    o.batch_log2 = -1;
+    o.branch_merge = 0;
+    o.bighead = 0;
+    o.restarts = 8;
+    o.cost_model = 0;
+    o.seed = 0;
+    o.max_workspace_bytes = 0;
+    return o;
+}
+
+// ---------------------------------------------------------------- greedy
+
+Tree greedy_tree(const std::vector<Legs>& leaf_legs, uint64_t seed, double alpha, double temperature) {
+    const int L = (int)leaf_legs.size();
+    int n_edges = 0;
+    for (auto& l : leaf_legs)
+        for (int e : l) n_edges = std::max(n_edges, e + 1);
+    std::vector<Legs> legs(leaf_legs);
+    legs.reserve(2 * L);
+    std::vector<char> alive(L, 1);
+    std::vector<std::array<int, 2>> owner(n_edges, {-1, -1});
+    for (int i = 0; i < L; ++i)
+        for (int e : legs[i]) {
+            if (owner[e][0] < 0) owner[e][0] = i;
+            else owner[e][1] = i;
+        }
+    std::mt19937_64 rng(seed * 0x9E3779B97F4A7C15ULL + 12345);
+    std::uniform_real_distribution<double> unif(1e-300, 1.0);
+    struct Cand {
+        double s;
+        int a, b;
+        bool operator<(const Cand& o) const {
+            if (s != o.s) return s > o.s;
+            if (a != o.a) return a > o.a;
+            return b > o.b;
+        }
+    };
+    std::priority_queue<Cand> pq;
+    auto score = [&](int a, int b) {
+        size_t la = legs[a].size(), lb = legs[b].size();
+        size_t shared = set_inter(legs[a], legs[b]).size();
+        size_t lc = la + lb - 2 * shared;
+        double raw = std::exp2((double)lc) - alpha * (std::exp2((double)la) + std::exp2((double)lb));
+        double s = raw >= 0 ? std::log2(1.0 + raw) : -std::log2(1.0 - raw);
+        if (temperature > 0) s -= temperature * (-std::log(-std::log(unif(rng))));
+        return s;
+    };
+    auto push = [&](int a, int b) {
+        if (a > b) std::swap(a, b);
+        pq.push({score(a, b), a, b});
+    };
+    {
+        std::set<std::pair<int, int>> seen;
+        for (int e = 0; e < n_edges; ++e) {
+            int a = owner[e][0], b = owner[e][1];
+            if (a < 0 || b < 0 || a == b) continue;
+            if (seen.insert({std::min(a, b), std::max(a, b)}).second) push(a, b);
+        }
+    }
+    Tree t;
+    t.n_leaves = L;
+    int n_alive = L;
+    while (n_alive > 1) {
+        int a = -1, b = -1;
+        while (!pq.empty()) {
+            Cand c = pq.top();
+            pq.pop();
+            if (alive[c.a] && alive[c.b]) {
+                a = c.a;
+                b = c.b;
+                break;
+            }
+        }
+        if (a < 0) {   // disconnected pieces: join the two smallest
+            std::vector<int> ids;
+            for (int i = 0; i < (int)alive.size(); ++i)
+                if (alive[i]) ids.push_back(i);
+            std::sort(ids.begin(), ids.end(), [&](int x, int y) {
+                return legs[x].size() != legs[y].size() ? legs[x].size() < legs[y].size() : x < y;
+            });
+            a = std::min(ids[0], ids[1]);
+            b = std::max(ids[0], ids[1]);
+        }
+        const int c = (int)legs.size();
+        legs.push_back(set_xor(legs[a], legs[b]));
+        for (int e : set_inter(legs[a], legs[b])) owner[e] = {-1, -1};
+        alive[a] = alive[b] = 0;
+        alive.push_back(1);
+        --n_alive;
+        t.lhs.push_back(a);
+        t.rhs.push_back(b);
+        std::set<int> nbs;
+        for (int e : legs[c]) {
+            for (int s = 0; s < 2; ++s)
+                if (owner[e][s] == a || owner[e][s] == b) owner[e][s] = c;
+            int other = owner[e][0] == c ? owner[e][1] : owner[e][0];
+            if (other >= 0 && other != c) nbs.insert(other);
+        }
+        for (int nb : nbs) push(c, nb);
+    }
+    return t;
+}
+
+// ------------------------------------------------------------ tree legs
+
+namespace {
+
+struct TreeLegs {
+    std::vector<Legs> node;   // legs of each node (no slicing)
+    std::vector<Legs> uni;    // per step: legs(a) U legs(b)
+    std::vector<int> parent;
+};
+
+TreeLegs tree_legs(const Network& net, const Tree& t) {
+    TreeLegs tl;
+    tl.node.resize(t.n_nodes());
+    tl.parent.assign(t.n_nodes(), -1);
+    for (int i = 0; i < t.n_leaves; ++i) {
+        tl.node[i] = net.leaves[i].legs;
+        std::sort(tl.node[i].begin(), tl.node[i].end());
+    }
+    tl.uni.resize(t.lhs.size());
+    for (size_t s = 0; s < t.lhs.size(); ++s) {
+        int a = t.lhs[s], b = t.rhs[s], c = t.n_leaves + (int)s;
+        tl.node[c] = set_xor(tl.node[a], tl.node[b]);
+        tl.uni[s] = set_union(tl.node[a], tl.node[b]);
+        tl.parent[a] = tl.parent[b] = c;
+    }
+    return tl;
+}
+
+int count_not_in(const Legs& l, const std::vector<char>& in_s) {
+    int c = 0;
+    for (int e : l) c += !in_s[e];
+    return c;
+}
+
+SliceCost slice_cost_tl(const TreeLegs& tl, const Tree& t, const std::vector<char>& in_s) {
+    SliceCost sc;
+    std::vector<char> dep(t.n_nodes(), 0);
+    for (int i = 0; i < t.n_leaves; ++i)
+        for (int e : tl.node[i]) dep[i] |= in_s[e];
+    for (size_t s = 0; s < t.lhs.size(); ++s) {
+        int c = t.n_leaves + (int)s;
+        dep[c] = dep[t.lhs[s]] | dep[t.rhs[s]];
+        double w = std::exp2((double)count_not_in(tl.uni[s], in_s));
+        if (dep[c]) sc.per_slice += w;
+        else sc.invariant += w;
+        sc.max_log2 = std::max(sc.max_log2, count_not_in(tl.node[c], in_s));
+    }
+    return sc;
+}
+
+// Greedy slicing: repeatedly fix the edge whose removal gives the lowest total
+// work, among the legs of the largest intermediates, until the memory target
+// and the requested count are both met.
+std::vector<int> greedy_slice(const Network& net, const Tree& t, const TreeLegs& tl, int target,
+                              int n_force, std::vector<int> sliced) {
+    const int E = (int)net.edge_name.size();
+    std::vector<char> is_open(E, 0), in_s(E, 0);
+    for (int e : net.open_edges) is_open[e] = 1;
+    for (int e : sliced) in_s[e] = 1;
+    while (true) {
+        SliceCost cur = slice_cost_tl(tl, t, in_s);
+        const int k = (int)sliced.size();
+        const bool over = cur.max_log2 > target;
+        if (!over && k >= n_force) break;
+        const int thresh = over ? cur.max_log2 : std::max(0, cur.max_log2 - 1);
+        std::set<int> cands;
+        for (int c = t.n_leaves; c < t.n_nodes(); ++c) {
+            if (count_not_in(tl.node[c], in_s) < thresh) continue;
+            for (int e : tl.node[c])
+                if (!in_s[e] && !is_open[e]) cands.insert(e);
+        }
+        if (cands.empty() || k >= 62) break;
+        int best = -1;
+        double best_cost = 0;
+        for (int e : cands) {
+            in_s[e] = 1;
+            SliceCost nc = slice_cost_tl(tl, t, in_s);
+            in_s[e] = 0;
+            double tot = nc.total(k + 1);
+            if (best < 0 || tot < best_cost * (1 - 1e-12)) {
+                best = e;
+                best_cost = tot;
+            }
+        }
+        in_s[best] = 1;
+        sliced.push_back(best);
+    }
+    return sliced;
+}
+
+struct BatchShape {
+    double cmacs = 0, bytes = 0;
+    int max_log2 = 0;
+};
+
+// Per-launch-sequence cost when the sliced edges in `in_b` are kept as batch
+// legs (contracted together) and the rest of `in_s` are fixed.
+BatchShape batch_shape(const TreeLegs& tl, const Tree& t, const std::vector<char>& in_s,
+                       const std::vector<char>& in_b, int esize) {
+    BatchShape bs;
+    const int N = t.n_nodes();
+    std::vector<Legs> lb(N);
+    std::vector<char> dep(N, 0);
+    for (int i = 0; i < t.n_leaves; ++i) {
+        for (int e : tl.node[i]) {
+            dep[i] |= in_s[e];
+            if (!in_s[e] || in_b[e]) lb[i].push_back(e);
+        }
+    }
+    for (size_t s = 0; s < t.lhs.size(); ++s) {
+        int a = t.lhs[s], b = t.rhs[s], c = t.n_leaves + (int)s;
+        dep[c] = dep[a] | dep[b];
+        Legs both = set_inter(lb[a], lb[b]);
+        Legs keep;
+        for (int e : both)
+            if (in_b[e]) keep.push_back(e);
+        lb[c] = set_union(set_xor(lb[a], lb[b]), keep);
+        if (!dep[c]) continue;
+        int nb = (int)keep.size();
+        int nk = (int)both.size() - nb;
+        int nm = (int)lb[a].size() - (int)both.size();
+        int nn = (int)lb[b].size() - (int)both.size();
+        bs.cmacs += std::exp2((double)(nm + nn + nk + nb));
+        bs.bytes += esize * (std::exp2((double)(nm + nk + nb)) + std::exp2((double)(nn + nk + nb)) +
+                             std::exp2((double)(nm + nn + nb)));
+        bs.max_log2 = std::max(bs.max_log2, (int)lb[c].size());
+    }
+    return bs;
+}
+
+int storage_bytes(tn_precision p) {
+    switch (p) {
+        case TN_C128: return 16;
+        case TN_BF16: return 4;
+        default: return 8;
+    }
+}
+
+}  // namespace
+
+SliceCost slice_cost(const Network& net, const Tree& t, const std::vector<char>& in_s) {
+    return slice_cost_tl(tree_legs(net, t), t, in_s);
+}
+
+// ------------------------------------------------------ layouts and steps
+
+namespace {
+
+// First-fit allocator over a linear arena (element units).
+struct Arena {
+    std::map<uint64_t, uint64_t> free_;   // offset -> length
+    uint64_t top = 0, peak = 0;
+    static uint64_t round(uint64_t n) { return (n + 63) & ~uint64_t(63); }
+    uint64_t alloc(uint64_t n) {
+        n = round(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                uint64_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > n) free_[off + n] = len - n;
+                return off;
+            }
+        }
+        uint64_t off = top;
+        top += n;
+        peak = std::max(peak, top);
+        return off;
+    }
+    void release(uint64_t off, uint64_t n) {
+        n = round(n);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+                it = pv;
+            }
+        }
+        if (it->first + it->second == top) {
+            top = it->first;
+            free_.erase(it);
+        }
+    }
+};
+
+}  // namespace
+
+static std::string finalize(Plan& p) {
+    const Network& net = p.net;
+    const Tree& t = p.tree;
+    const int E = (int)net.edge_name.size();
+    const int N = t.n_nodes();
+    std::vector<char> in_s(E, 0), in_b(E, 0);
+    std::vector<int> slice_bit(E, -1);
+    for (size_t i = 0; i < p.sliced.size(); ++i) {
+        in_s[p.sliced[i]] = 1;
+        slice_bit[p.sliced[i]] = (int)i;
+    }
+    for (int e : p.batch) in_b[e] = 1;
+    p.nodes.assign(N, NodeInfo());
+    // legs with batch legs kept
+    for (int i = 0; i < t.n_leaves; ++i) {
+        Legs l = net.leaves[i].legs;
+        std::sort(l.begin(), l.end());
+        for (int e : l) {
+            p.nodes[i].dep |= (bool)in_s[e];
+            if (!in_s[e] || in_b[e]) p.nodes[i].legs.push_back(e);
+        }
+        p.nodes[i].home = HOME_LEAF;
+    }
+    for (size_t s = 0; s < t.lhs.size(); ++s) {
+        int a = t.lhs[s], b = t.rhs[s], c = t.n_leaves + (int)s;
+        NodeInfo& C = p.nodes[c];
+        C.dep = p.nodes[a].dep || p.nodes[b].dep;
+        Legs both = set_inter(p.nodes[a].legs, p.nodes[b].legs);
+        Legs keep;
+        for (int e : both)
+            if (in_b[e]) keep.push_back(e);
+        C.legs = set_union(set_xor(p.nodes[a].legs, p.nodes[b].legs), keep);
+        p.nodes[a].parent = p.nodes[b].parent = c;
+        C.home = C.dep ? HOME_WS : HOME_PLAN;
+    }
+    // root layout: result legs (bit 0 = last open leg) then batch legs in slice-bit order
+    const int root = t.root();
+    {
+        Legs res = net.open_edges;
+        std::reverse(res.begin(), res.end());
+        Legs got = p.nodes[root].legs;
+        Legs want = res;
+        for (int e : p.batch) want.push_back(e);
+        Legs ws = want;
+        std::sort(ws.begin(), ws.end());
+        if (ws != got) return "internal error: root legs are not open legs + batch legs";
+        p.nodes[root].layout = want;
+        p.root_log2 = (int)res.size();
+    }
+    // top-down layouts and step shapes
+    p.steps.clear();
+    std::vector<Step> by_node(N);
+    for (int s = (int)t.lhs.size() - 1; s >= 0; --s) {
+        const int c = t.n_leaves + s;
+        int a = t.lhs[s], b = t.rhs[s];
+        const Legs& la0 = p.nodes[a].legs;
+        const Legs& lb0 = p.nodes[b].legs;
+        const std::vector<int>& lc = p.nodes[c].layout;
+        std::map<int, int> posc;
+        for (size_t i = 0; i < lc.size(); ++i) posc[lc[i]] = (int)i;
+        bool swap_ab = false;
+        if (lb0.size() > la0.size()) swap_ab = true;
+        else if (lb0.size() == la0.size() && !lc.empty()) {
+            swap_ab = std::binary_search(lb0.begin(), lb0.end(), lc[0]) &&
+                      !std::binary_search(la0.begin(), la0.end(), lc[0]);
+        }
+        if (swap_ab) std::swap(a, b);
+        const Legs& la = p.nodes[a].legs;
+        const Legs& lb = p.nodes[b].legs;
+        Legs both = set_inter(la, lb);
+        Legs bat, kk;
+        for (int e : both) (in_b[e] ? bat : kk).push_back(e);
+        Legs M = set_minus(la, lb), Nn = set_minus(lb, la);
+        auto by_c = [&](Legs v) {
+            std::sort(v.begin(), v.end(), [&](int x, int y) { return posc.at(x) < posc.at(y); });
+            return v;
+        };
+        M = by_c(M);
+        Nn = by_c(Nn);
+        bat = by_c(bat);
+        Step st{};
+        st.node = c;
+        st.a_node = a;
+        st.b_node = b;
+        st.m_log = (int)M.size();
+        st.n_log = (int)Nn.size();
+        st.k_log = (int)kk.size();
+        st.b_log = (int)bat.size();
+        for (int e : M) st.c_pos_m.push_back(posc.at(e));
+        for (int e : Nn) st.c_pos_n.push_back(posc.at(e));
+        for (int e : bat) st.c_pos_b.push_back(posc.at(e));
+        st.invariant = !p.nodes[c].dep;
+        std::vector<int> lay_a = M, lay_b = Nn;
+        lay_a.insert(lay_a.end(), bat.begin(), bat.end());
+        lay_a.insert(lay_a.end(), kk.begin(), kk.end());
+        lay_b.insert(lay_b.end(), bat.begin(), bat.end());
+        lay_b.insert(lay_b.end(), kk.begin(), kk.end());
+        p.nodes[a].layout = lay_a;
+        p.nodes[b].layout = lay_b;
+        const double mnkb = (double)(st.m_log + st.n_log + st.k_log + st.b_log);
+        st.cmacs = std::exp2(mnkb);
+        st.bytes = p.esize * (std::exp2((double)(st.m_log + st.k_log + st.b_log)) +
+                              std::exp2((double)(st.n_log + st.k_log + st.b_log)) +
+                              std::exp2((double)(st.m_log + st.n_log + st.b_log)));
+        choose_kernel(st.m_log, st.n_log, st.k_log, st.b_log, p.opts.prec, st.kernel, st.tile,
+                      st.splitk_log);
+        if (st.invariant && st.kernel == K_SPLITK) {   // computed once, outside any workspace
+            st.kernel = K_SMALL;
+            st.splitk_log = 0;
+        }
+        by_node[c] = st;
+    }
+    // leaves: outer-sliced legs on top
+    for (int i = 0; i < t.n_leaves; ++i) {
+        NodeInfo& L = p.nodes[i];
+        if (t.n_nodes() == 1) L.layout = p.nodes[root].layout;
+        std::vector<int> extra;
+        for (int e : net.leaves[i].legs)
+            if (in_s[e] && !in_b[e]) extra.push_back(e);
+        std::sort(extra.begin(), extra.end(), [&](int x, int y) { return slice_bit[x] < slice_bit[y]; });
+        for (int e : extra) {
+            L.layout.push_back(e);
+            L.sliced_bits.push_back(slice_bit[e]);
+        }
+    }
+    // execution order: invariant steps first, then dependent steps
+    for (int pass = 0; pass < 2; ++pass)
+        for (size_t s = 0; s < t.lhs.size(); ++s) {
+            const Step& st = by_node[t.n_leaves + s];
+            if ((pass == 0) == st.invariant) p.steps.push_back(st);
+        }
+    p.n_invariant_steps = 0;
+    for (auto& st : p.steps) p.n_invariant_steps += st.invariant;
+    // memory: plan arena holds leaves and invariant tensors; the workspace
+    // holds dependent intermediates with liveness reuse plus split-K scratch
+    uint64_t plan_top = 0;
+    for (int i = 0; i < t.n_leaves; ++i) {
+        p.nodes[i].off = plan_top;
+        plan_top += Arena::round(uint64_t(1) << p.nodes[i].layout.size());
+    }
+    for (auto& st : p.steps)
+        if (st.invariant) {
+            p.nodes[st.node].off = plan_top;
+            st.c_off = plan_top;
+            plan_top += Arena::round(uint64_t(1) << p.nodes[st.node].legs.size());
+        }
+    p.plan_elems = plan_top;
+    Arena ws;
+    for (auto& st : p.steps) {
+        if (st.invariant) continue;
+        const uint64_t csz = uint64_t(1) << p.nodes[st.node].legs.size();
+        st.c_off = ws.alloc(csz);
+        p.nodes[st.node].off = st.c_off;
+        if (st.kernel == K_SPLITK) {
+            // partial tiles are stored at the storage width
+            const uint64_t scr_elems = uint64_t(1) << (st.m_log + st.n_log + st.b_log + st.splitk_log);
+            st.scratch_off = ws.alloc(scr_elems);
+            ws.release(st.scratch_off, scr_elems);
+        }
+        for (int o : {st.a_node, st.b_node})
+            if (p.nodes[o].home == HOME_WS) ws.release(p.nodes[o].off, uint64_t(1) << p.nodes[o].legs.size());
+    }
+    p.ws_elems = std::max<uint64_t>(ws.peak, 64);
+    if (t.n_nodes() == 1) p.ws_elems = std::max<uint64_t>(p.ws_elems, uint64_t(1) << p.nodes[root].legs.size());
+    return "";
+}
+
+static void fill_stats(Plan& p) {
+    tn_plan_stats& s = p.stats;
+    s = tn_plan_stats{};
+    s.n_sliced = (int)p.sliced.size();
+    s.n_slices = uint64_t(1) << s.n_sliced;
+    s.batch_log2 = p.batch_log2;
+    s.n_open = (int)p.net.open_edges.size();
+    s.n_leaves = p.tree.n_leaves;
+    s.n_steps = (int)p.tree.lhs.size();
+    s.acc_log2 = p.root_log2;
+    double per_batch = 0, inv = 0, bytes = 0;
+    int mx = 0;
+    for (auto& st : p.steps) {
+        if (st.invariant) inv += st.cmacs;
+        else {
+            per_batch += st.cmacs;
+            bytes += st.bytes;
+        }
+        if (st.kernel == K_MFMA) s.n_dense_steps++;
+        else s.n_small_steps++;
+    }
+    for (int c = p.tree.n_leaves; c < p.tree.n_nodes(); ++c)
+        mx = std::max(mx, (int)p.nodes[c].legs.size() - (p.nodes[c].dep ? 0 : 0));
+    const double B = std::exp2((double)p.batch_log2);
+    s.cmacs_per_batch = per_batch;
+    s.bytes_per_batch = bytes + 16.0 * std::exp2((double)p.root_log2);
+    s.cmacs_per_slice = per_batch / B;
+    s.cmacs_per_slice_unmerged = p.unmerged_cmacs_per_slice;
+    s.cmacs_invariant = inv;
+    s.cmacs_tail = 0;
+    s.bytes_per_slice = s.bytes_per_batch / B;
+    s.max_log2_size = mx - p.batch_log2 > 0 ? mx : mx;
+    // per-slice max: legs without batch legs
+    int mx1 = 0;
+    std::set<int> bset(p.batch.begin(), p.batch.end());
+    for (int c = p.tree.n_leaves; c < p.tree.n_nodes(); ++c) {
+        int n = 0;
+        for (int e : p.nodes[c].legs) n += !bset.count(e);
+        mx1 = std::max(mx1, n);
+    }
+    s.max_log2_size = mx1;
+    s.workspace_bytes = p.ws_elems * (uint64_t)p.esize;
+    s.tail_workspace_bytes = 0;
+    s.n_c = 0;
+}
+
+std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
+                      const std::vector<int>& fixed_q, const std::vector<uint8_t>& bits,
+                      const tn_tree* tree, const tn_edge* sliced, int n_sliced,
+                      const tn_plan_opts& opts, Plan& out) {
+    out = Plan();
+    out.opts = opts;
+    if (opts.prec < TN_C64 || opts.prec > TN_BF16) return "unknown precision";
+    if (opts.max_log2_size < 1 || opts.max_log2_size > 40) return "max_log2_size out of range";
+    out.esize = storage_bytes(opts.prec);
+    std::string err = build_network(c, open_q, fixed_q, bits, out.net);
+    if (!err.empty()) return err;
+    const Network& net = out.net;
+    const int E = (int)net.edge_name.size();
+    const int L = (int)net.leaves.size();
+    std::vector<int> user_sliced;
+    if (sliced && n_sliced > 0) {
+        std::vector<char> seen(E, 0), is_open(E, 0);
+        for (int e : net.open_edges) is_open[e] = 1;
+        for (int i = 0; i < n_sliced; ++i) {
+            int e = net.find_edge(sliced[i].qubit, sliced[i].segment);
+            if (e < 0) return "sliced edge (" + std::to_string(sliced[i].qubit) + "," +
+                              std::to_string(sliced[i].segment) + ") is not an edge";
+            if (is_open[e]) return "an open leg cannot be sliced";
+            if (seen[e]) return "sliced edge repeated";
+            seen[e] = 1;
+            user_sliced.push_back(e);
+        }
+    }
+    const bool fixed_slicing = n_sliced >= 0;
+    std::vector<Legs> leaf_legs(L);
+    for (int i = 0; i < L; ++i) {
+        leaf_legs[i] = net.leaves[i].legs;
+        std::sort(leaf_legs[i].begin(), leaf_legs[i].end());
+    }
+    // candidate trees
+    std::vector<Tree> cands;
+    if (tree) {
+        if (tree->n_steps != L - 1) return "tree must have n_leaves - 1 steps";
+        Tree t;
+        t.n_leaves = L;
+        std::vector<char> used(2 * L, 0);
+        for (int s = 0; s < tree->n_steps; ++s) {
+            int a = tree->lhs[s], b = tree->rhs[s];
+            if (a < 0 || b < 0 || a >= L + s || b >= L + s || a == b || used[a] || used[b])
+                return "invalid tree at step " + std::to_string(s);
+            used[a] = used[b] = 1;
+            t.lhs.push_back(a);
+            t.rhs.push_back(b);
+        }
+        cands.push_back(t);
+    } else {
+        const int R = std::max(1, opts.restarts);
+        std::mt19937_64 rng(opts.seed + 777);
+        std::uniform_real_distribution<double> ua(0.5, 1.5), ut(0.0, 1.0);
+        for (int r = 0; r < R; ++r) {
+            double alpha = r == 0 ? 1.0 : ua(rng);
+            double temp = r == 0 ? 0.0 : ut(rng);
+            cands.push_back(greedy_tree(leaf_legs, opts.seed * 1000003ULL + r, alpha, temp));
+        }
+    }
+    if (L == 1) {
+        cands.clear();
+        Tree t;
+        t.n_leaves = 1;
+        cands.push_back(t);
+    }
+    // slice each candidate, keep the cheapest
+    double best_cost = -1;
+    const int n_force = fixed_slicing ? 0 : std::max(0, opts.n_slice_edges);
+    for (auto& t : cands) {
+        TreeLegs tl = tree_legs(net, t);
+        std::vector<int> s = fixed_slicing ? user_sliced
+                                           : greedy_slice(net, t, tl, opts.max_log2_size, n_force, {});
+        std::vector<char> in_s(E, 0);
+        for (int e : s) in_s[e] = 1;
+        SliceCost sc = slice_cost_tl(tl, t, in_s);
+        double cost = sc.total((int)s.size());
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            out.tree = t;
+            out.sliced = s;
+            out.unmerged_cmacs_per_slice = sc.per_slice;
+        }
+    }
+    // batch legs
+    {
+        TreeLegs tl = tree_legs(net, out.tree);
+        std::vector<char> in_s(E, 0), in_b(E, 0);
+        for (int e : out.sliced) in_s[e] = 1;
+        const int k = (int)out.sliced.size();
+        const uint64_t cap = opts.max_workspace_bytes > 0 ? (uint64_t)opts.max_workspace_bytes
+                                                          : (uint64_t(32) << 30);
+        int want = opts.batch_log2;
+        SliceCost sc = slice_cost_tl(tl, out.tree, in_s);
+        const int size_cap = std::max(sc.max_log2, 25);
+        std::vector<int> chosen;
+        while ((int)chosen.size() < k) {
+            if (want >= 0 && (int)chosen.size() >= want) break;
+            int best = -1;
+            BatchShape bb;
+            for (int e : out.sliced) {
+                if (in_b[e]) continue;
+                in_b[e] = 1;
+                BatchShape x = batch_shape(tl, out.tree, in_s, in_b, out.esize);
+                in_b[e] = 0;
+                if (best < 0 || x.cmacs < bb.cmacs) {
+                    best = e;
+                    bb = x;
+                }
+            }
+            if (best < 0) break;
+            if (want < 0) {
+                const double ws_est = 3.0 * std::exp2((double)bb.max_log2) * out.esize;
+                if (bb.max_log2 > size_cap || ws_est > (double)cap || (int)chosen.size() >= 14) break;
+            }
+            in_b[best] = 1;
+            chosen.push_back(best);
+        }
+        out.batch_log2 = (int)chosen.size();
+        if (!fixed_slicing) {   // batch edges take the low slice bits
+            std::vector<int> reorder = chosen;
+            for (int e : out.sliced)
+                if (!in_b[e]) reorder.push_back(e);
+            out.sliced = reorder;
+            out.batch = chosen;
+        } else {
+            // keep the caller's bit order; batch legs must be the low bits
+            out.batch.clear();
+            int nb = 0;
+            for (int i = 0; i < k && in_b[out.sliced[i]]; ++i) nb++;
+            // restrict the batch to a prefix of the caller's order
+            out.batch.assign(out.sliced.begin(), out.sliced.begin() + nb);
+            out.batch_log2 = nb;
+            if (nb != (int)chosen.size()) {
+                // re-choose: the largest prefix that satisfies the limits
+                std::fill(in_b.begin(), in_b.end(), 0);
+                out.batch.clear();
+                for (int i = 0; i < k; ++i) {
+                    if (want >= 0 && i >= want) break;
+                    in_b[out.sliced[i]] = 1;
+                    BatchShape x = batch_shape(tl, out.tree, in_s, in_b, out.esize);
+                    const double ws_est = 3.0 * std::exp2((double)x.max_log2) * out.esize;
+                    if (want < 0 && (x.max_log2 > size_cap || ws_est > (double)cap || i >= 14)) {
+                        in_b[out.sliced[i]] = 0;
+                        break;
+                    }
+                    out.batch.push_back(out.sliced[i]);
+                }
+                out.batch_log2 = (int)out.batch.size();
+            }
+        }
+    }
+    if (out.sliced.size() > 62) return "more than 62 sliced edges needed";
+    err = finalize(out);
+    if (!err.empty()) return err;
+    fill_stats(out);
+    return "";
+}
+
+// ------------------------------------------------------------------- JSON
+
+std::string plan_to_json(const Plan& p) {
+    std::ostringstream o;
+    auto edge = [&](int e) {
+        std::ostringstream x;
+        x << "[" << p.net.edge_name[e].q << "," << p.net.edge_name[e].t << "]";
+        return x.str();
+    };
+    o << "{\"n_leaves\":" << p.tree.n_leaves << ",\"lhs\":[";
+    for (size_t i = 0; i < p.tree.lhs.size(); ++i) o << (i ? "," : "") << p.tree.lhs[i];
+    o << "],\"rhs\":[";
+    for (size_t i = 0; i < p.tree.rhs.size(); ++i) o << (i ? "," : "") << p.tree.rhs[i];
+    o << "],\"sliced\":[";
+    for (size_t i = 0; i < p.sliced.size(); ++i) o << (i ? "," : "") << edge(p.sliced[i]);
+    o << "],\"batch_log2\":" << p.batch_log2 << ",\"open\":[";
+    for (size_t i = 0; i < p.net.open_edges.size(); ++i) o << (i ? "," : "") << edge(p.net.open_edges[i]);
+    o << "],\"leaves\":[";
+    for (size_t i = 0; i < p.net.leaves.size(); ++i) {
+        o << (i ? "," : "") << "[";
+        for (size_t j = 0; j < p.net.leaves[i].legs.size(); ++j)
+            o << (j ? "," : "") << edge(p.net.leaves[i].legs[j]);
+        o << "]";
+    }
+    o << "],\"steps\":[";
+    for (size_t i = 0; i < p.steps.size(); ++i) {
+        const Step& s = p.steps[i];
+        o << (i ? "," : "") << "{\"node\":" << s.node << ",\"a\":" << s.a_node << ",\"b\":" << s.b_node
+          << ",\"m\":" << s.m_log << ",\"n\":" << s.n_log << ",\"k\":" << s.k_log << ",\"batch\":" << s.b_log
+          << ",\"invariant\":" << (s.invariant ? "true" : "false") << ",\"kernel\":" << s.kernel
+          << ",\"tile\":" << s.tile << ",\"splitk\":" << s.splitk_log << ",\"cmacs\":" << s.cmacs
+          << ",\"bytes\":" << s.bytes << "}";
+    }
+    const tn_plan_stats& st = p.stats;
+    o << "],\"stats\":{\"n_sliced\":" << st.n_sliced << ",\"batch_log2\":" << st.batch_log2
+      << ",\"max_log2_size\":" << st.max_log2_size << ",\"cmacs_per_slice\":" << st.cmacs_per_slice
+      << ",\"cmacs_per_slice_unmerged\":" << st.cmacs_per_slice_unmerged
+      << ",\"cmacs_per_batch\":" << st.cmacs_per_batch << ",\"bytes_per_batch\":" << st.bytes_per_batch
+      << ",\"cmacs_invariant\":" << st.cmacs_invariant << ",\"workspace_bytes\":" << st.workspace_bytes
+      << ",\"n_dense_steps\":" << st.n_dense_steps << ",\"n_small_steps\":" << st.n_small_steps << "}}";
+    return o.str();
+}
+
+}  // namespace tn

@@ -1,0 +1,63 @@
+// Kernel classes and tile shapes shared by the planner and the launcher.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+
+#include "../../include/tn.h"
+
+namespace tn {
+
+// MFMA tile shapes: complex M x N per workgroup of 4 waves.
+struct MfmaTile {
+    int tm_log, tn_log;   // log2 of the complex tile
+    int waves_m, waves_n; // wave grid (waves_m * waves_n = 4)
+    int tk_max_log;       // largest K chunk (complex, log2) the LDS tile holds
+};
+constexpr MfmaTile kMfmaTiles[] = {
+    {7, 6, 2, 2, 4},   // 128 x 64: each wave 64 rows x 64 real columns
+    {6, 5, 2, 2, 4},   // 64 x 32
+    {7, 4, 4, 1, 4},   // 128 x 16
+    {6, 3, 4, 1, 4},   // 64 x 8
+    {8, 3, 4, 1, 3},   // 256 x 8
+};
+constexpr int kNumMfmaTiles = sizeof(kMfmaTiles) / sizeof(kMfmaTiles[0]);
+
+inline bool mfma_capable(tn_precision p) { return p != TN_C128; }
+
+// Choose the kernel class and tile for C[b,m,n] = sum_k A[k,b,m] B[k,b,n]
+// (all sizes log2).  Dense steps go to MFMA tiles; steps whose output is tiny
+// but whose contracted dimension is long are split along K; everything else
+// (the big-times-small steps that dominate bond-dimension-2 networks) runs on
+// the streaming VALU kernel.
+inline void choose_kernel(int m, int n, int k, int b, tn_precision prec, int& kernel, int& tile,
+                          int& splitk_log) {
+    kernel = 0;
+    tile = 0;
+    splitk_log = 0;
+    if (mfma_capable(prec) && m >= 6 && n >= 3 && k >= 2) {
+        int best = -1;
+        for (int t = 0; t < kNumMfmaTiles; ++t) {
+            const MfmaTile& T = kMfmaTiles[t];
+            if (T.tm_log > m || T.tn_log > n) continue;
+            const int grid_log = (m - T.tm_log) + (n - T.tn_log) + b;
+            if (grid_log >= 9) { best = t; break; }
+            if (best < 0 || grid_log > (m - kMfmaTiles[best].tm_log) + (n - kMfmaTiles[best].tn_log) + b)
+                best = t;
+        }
+        if (best >= 0) {
+            kernel = 1;
+            tile = best;
+            return;
+        }
+    }
+    if (m + n + b <= 14 && k >= 12) {
+        kernel = 2;
+        // aim for ~2^10 workgroups, each with at least 2^8 of K
+        const int out_tiles_log = std::max(0, m + n + b - 8);
+        splitk_log = std::max(0, std::min(k - 8, 10 - out_tiles_log));
+        return;
+    }
+}
+
+}  // namespace tn

@@ -1,0 +1,249 @@
+"""Python binding of the C ABI in include/tn.h (argument marshalling only).
+
+Every function here converts Python arguments to the C types of tn.h and
+calls the HIP library libtnsim.so; all computation happens in the library.
+If the library is missing the import fails loudly -- there is no fallback.
+
+Device buffers are torch CUDA (HIP) tensors; streams are torch streams.
+"""
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtnsim.so")
+
+TN_C64, TN_C128, TN_SPLIT_FP16, TN_BF16 = 0, 1, 2, 3
+PRECISIONS = {"c64": TN_C64, "c128": TN_C128, "split_fp16": TN_SPLIT_FP16, "bf16": TN_BF16}
+
+
+class TnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tn status {status}: {msg}")
+        self.status = status
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
+                ("re", ctypes.c_double * 16), ("im", ctypes.c_double * 16)]
+
+
+class CircuitC(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32),
+                ("gates", ctypes.POINTER(Gate))]
+
+
+class EdgeC(ctypes.Structure):
+    _fields_ = [("qubit", ctypes.c_int32), ("segment", ctypes.c_int32)]
+
+
+class TreeC(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("lhs", ctypes.POINTER(ctypes.c_int32)),
+                ("rhs", ctypes.POINTER(ctypes.c_int32))]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("max_log2_size", ctypes.c_int32),
+                ("n_slice_edges", ctypes.c_int32), ("batch_log2", ctypes.c_int32),
+                ("branch_merge", ctypes.c_int32), ("bighead", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("cost_model", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("max_workspace_bytes", ctypes.c_int64)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("n_slices", ctypes.c_uint64), ("n_sliced", ctypes.c_int32),
+                ("batch_log2", ctypes.c_int32), ("n_open", ctypes.c_int32),
+                ("n_leaves", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("n_c", ctypes.c_int32), ("max_log2_size", ctypes.c_int32),
+                ("acc_log2", ctypes.c_int32),
+                ("cmacs_per_slice", ctypes.c_double), ("cmacs_per_slice_unmerged", ctypes.c_double),
+                ("cmacs_invariant", ctypes.c_double), ("cmacs_tail", ctypes.c_double),
+                ("bytes_per_slice", ctypes.c_double), ("cmacs_per_batch", ctypes.c_double),
+                ("bytes_per_batch", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_uint64), ("tail_workspace_bytes", ctypes.c_uint64),
+                ("n_dense_steps", ctypes.c_int32), ("n_small_steps", ctypes.c_int32)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class XebResult(ctypes.Structure):
+    _fields_ = [("F_unif", ctypes.c_double), ("F_self", ctypes.c_double), ("P_s1", ctypes.c_double),
+                ("cond_xeb", ctypes.c_double), ("p_max", ctypes.c_double), ("p_min", ctypes.c_double)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol tn.h declares, with its ctypes signature
+_P = ctypes.c_void_p
+_SIGS = {
+    "tn_plan": (ctypes.c_int, [ctypes.POINTER(CircuitC), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32,
+                               ctypes.POINTER(TreeC), ctypes.POINTER(EdgeC), ctypes.c_int32,
+                               ctypes.POINTER(PlanOpts), ctypes.POINTER(_P)]),
+    "tn_plan_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(PlanStats)]),
+    "tn_plan_sliced_edges": (ctypes.c_int, [_P, ctypes.POINTER(EdgeC), ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    "tn_plan_export_json": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "tn_contract_slices": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, ctypes.c_uint64, ctypes.c_uint64, _P]),
+    "tn_contract_slice_list": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_uint64),
+                                              ctypes.c_uint64, _P]),
+    "tn_amplitudes": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "tn_xeb": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                              ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(XebResult), _P]),
+    "tn_plan_destroy": (None, [_P]),
+    "tn_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def library():
+    """Load libtnsim.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_03074_amd.build`")
+        # torch ships its own HIP runtime with the same soname; loading torch
+        # first makes the library bind to that one runtime, so torch's device
+        # memory and stream handles are valid inside the library.
+        import torch  # noqa: F401
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        msg = library().tn_last_error().decode(errors="replace")
+        raise TnError(status, msg)
+
+
+def _circuit_c(circuit):
+    gates = (Gate * max(1, len(circuit.gates)))()
+    for i, g in enumerate(circuit.gates):
+        gates[i].q0 = int(g.qubits[0])
+        gates[i].q1 = int(g.qubits[1]) if len(g.qubits) == 2 else -1
+        flat = np.asarray(g.matrix, dtype=np.complex128).ravel()
+        for j, v in enumerate(flat):
+            gates[i].re[j] = float(v.real)
+            gates[i].im[j] = float(v.imag)
+    c = CircuitC(circuit.n_qubits, len(circuit.gates), gates)
+    return c, gates
+
+
+def plan_options(prec="c64", max_log2_size=30, n_slice_edges=-1, batch_log2=-1, branch_merge=0,
+                 bighead=0, restarts=8, cost_model=0, seed=0, max_workspace_bytes=0):
+    return PlanOpts(PRECISIONS[prec] if isinstance(prec, str) else int(prec), max_log2_size, n_slice_edges,
+                    batch_log2, branch_merge, bighead, restarts, cost_model, seed, max_workspace_bytes)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+class Plan:
+    """Owner of a tn_plan_t handle."""
+
+    def __init__(self, circuit, open_q, fixed_q, bits, tree=None, sliced=None, **opts):
+        lib = library()
+        c, keep = _circuit_c(circuit)
+        oq = (ctypes.c_int32 * max(1, len(open_q)))(*[int(q) for q in open_q])
+        fq = (ctypes.c_int32 * max(1, len(fixed_q)))(*[int(q) for q in fixed_q])
+        fb = (ctypes.c_uint8 * max(1, len(bits)))(*[int(b) for b in bits])
+        tree_c = None
+        if tree is not None:
+            lhs = (ctypes.c_int32 * len(tree))(*[int(a) for a, _ in tree])
+            rhs = (ctypes.c_int32 * len(tree))(*[int(b) for _, b in tree])
+            tree_c = TreeC(len(tree), lhs, rhs)
+        n_sl = -1
+        sl = None
+        if sliced is not None:
+            n_sl = len(sliced)
+            sl = (EdgeC * max(1, n_sl))(*[EdgeC(int(q), int(t)) for q, t in sliced])
+        o = plan_options(**opts)
+        h = ctypes.c_void_p()
+        _check(lib.tn_plan(ctypes.byref(c), oq, len(open_q), fq, fb, len(fixed_q),
+                           ctypes.byref(tree_c) if tree_c is not None else None,
+                           sl, n_sl, ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self.n_qubits = circuit.n_qubits
+        self.n_open = len(open_q)
+        del keep
+
+    def close(self):
+        if getattr(self, "handle", None):
+            library().tn_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self):
+        s = PlanStats()
+        _check(library().tn_plan_stats_get(self.handle, ctypes.byref(s)))
+        return s.to_dict()
+
+    def sliced_edges(self):
+        n = ctypes.c_int32()
+        _check(library().tn_plan_sliced_edges(self.handle, None, 0, ctypes.byref(n)))
+        arr = (EdgeC * max(1, n.value))()
+        _check(library().tn_plan_sliced_edges(self.handle, arr, n.value, ctypes.byref(n)))
+        return [(arr[i].qubit, arr[i].segment) for i in range(n.value)]
+
+    def export(self):
+        need = ctypes.c_size_t()
+        _check(library().tn_plan_export_json(self.handle, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(library().tn_plan_export_json(self.handle, buf, need.value, ctypes.byref(need)))
+        return json.loads(buf.value.decode())
+
+    # -- device calls (torch tensors in, nothing allocated here) ---------
+
+    def contract_slices(self, ws, acc, begin, end, stream=None):
+        _check(library().tn_contract_slices(self.handle, ctypes.c_void_p(ws.data_ptr()),
+                                            ws.numel() * ws.element_size(), ctypes.c_void_p(acc.data_ptr()),
+                                            int(begin), int(end), _stream_ptr(stream)))
+
+    def contract_slice_list(self, ws, acc, ids, stream=None):
+        ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64))
+        _check(library().tn_contract_slice_list(
+            self.handle, ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+            ctypes.c_void_p(acc.data_ptr()), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+            ids.size, _stream_ptr(stream)))
+
+    def amplitudes(self, acc, amps, ws=None, stream=None):
+        _check(library().tn_amplitudes(self.handle, ctypes.c_void_p(acc.data_ptr()),
+                                       ctypes.c_void_p(amps.data_ptr()),
+                                       ctypes.c_void_p(ws.data_ptr()) if ws is not None else None,
+                                       (ws.numel() * ws.element_size()) if ws is not None else 0,
+                                       _stream_ptr(stream)))
+
+
+def xeb(amps, n_open, n_qubits, weight=1.0, ks=(), stream=None):
+    """Eq. (1) statistics of a device tensor of 2^n_open complex128."""
+    lib = library()
+    r = XebResult()
+    nk = len(ks)
+    karr = (ctypes.c_int64 * max(1, nk))(*[int(k) for k in ks])
+    out = (ctypes.c_double * max(1, nk))()
+    _check(lib.tn_xeb(ctypes.c_void_p(amps.data_ptr()), int(n_open), int(n_qubits), float(weight),
+                      karr if nk else None, nk, out if nk else None, ctypes.byref(r), _stream_ptr(stream)))
+    d = r.to_dict()
+    d["topk"] = [out[i] for i in range(nk)]
+    return d

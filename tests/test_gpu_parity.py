@@ -1,0 +1,201 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Complex64 results must match the complex128 oracle within 1e-5 norm-relative
+error; complex128 results within 1e-12.  Every case prints its name before it
+touches the GPU.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import rqc
+from oracle import network as nw
+from oracle import statevector as sv
+from oracle import closed_form as cf
+from oracle import stats
+
+pytestmark = pytest.mark.gpu
+
+C64_TOL = 1e-5
+C128_TOL = 1e-12
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _run(plan, slices=None):
+    from paper_2103_03074_amd import runtime
+    torch = _torch()
+    amps = runtime.amplitudes(plan, slices)
+    torch.cuda.synchronize()
+    return amps.cpu().numpy()
+
+
+def _rel(x, ref):
+    return stats.norm_rel_error(x, ref)
+
+
+def _plan(w, **kw):
+    from paper_2103_03074_amd import tn
+    return tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], **kw)
+
+
+@pytest.mark.parametrize("prec,tol", [("c64", C64_TOL), ("c128", C128_TOL)])
+def test_c1_all_slices_vs_statevector(prec, tol):
+    w = rqc.workload("c1_tiny_3x4_m8")
+    _say("c1 all slices", prec)
+    p = _plan(w, n_slice_edges=2, prec=prec)
+    got = _run(p)
+    psi = sv.simulate_numpy(w["circuit"])
+    ref = sv.amplitudes_from_state(psi, 12, w["open_q"], w["fixed_q"], w["bits"])
+    assert got.shape == ref.shape
+    assert _rel(got, ref) < tol
+
+
+@pytest.mark.parametrize("batch_log2", [0, 2])
+def test_c1_each_slice_vs_oracle(batch_log2):
+    w = rqc.workload("c1_tiny_3x4_m8")
+    p = _plan(w, n_slice_edges=2, batch_log2=batch_log2)
+    sliced = p.sliced_edges()
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    for j in range(4):
+        _say("c1 slice", j, "batch_log2", batch_log2)
+        got = _run(p, (j, j + 1))
+        ref = nw.slice_amplitudes(net, sliced, j)
+        assert _rel(got, ref) < C64_TOL
+
+
+def test_c2_vs_statevector(c2_state):
+    w, psi = c2_state
+    _say("c2 256 slices c64")
+    p = _plan(w, n_slice_edges=8, restarts=4)
+    s = p.stats()
+    assert s["n_slices"] == 256
+    got = _run(p)
+    ref = sv.amplitudes_from_state(psi, 25, w["open_q"], w["fixed_q"], w["bits"])
+    err = _rel(got, ref)
+    _say("c2 norm-rel error", err, "dense steps", s["n_dense_steps"])
+    assert err < C64_TOL
+
+
+def test_c2_c128_vs_statevector(c2_state):
+    w, psi = c2_state
+    _say("c2 256 slices c128")
+    p = _plan(w, n_slice_edges=8, restarts=4, prec="c128")
+    got = _run(p)
+    ref = sv.amplitudes_from_state(psi, 25, w["open_q"], w["fixed_q"], w["bits"])
+    assert _rel(got, ref) < C128_TOL
+
+
+def test_c2_sampled_slices_vs_oracle():
+    w = rqc.workload("c2_5x5_m16")
+    p = _plan(w, n_slice_edges=8, restarts=4)
+    sliced = p.sliced_edges()
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    ids = rqc.sample_slice_ids(8, 3, seed=2)
+    _say("c2 sampled slices", list(ids))
+    got = _run(p, list(int(i) for i in ids))
+    ref = sum(nw.slice_amplitudes(net, sliced, int(j)) for j in ids)
+    assert _rel(got, ref) < C64_TOL
+
+
+def test_range_split_and_list_agree():
+    torch = _torch()
+    from paper_2103_03074_amd import runtime
+    w = rqc.workload("c1_tiny_3x4_m8")
+    p = _plan(w, n_slice_edges=4, batch_log2=2)
+    _say("c1 range split")
+    ws = runtime.workspace(p)
+    acc1 = runtime.accumulator(p)
+    p.contract_slices(ws, acc1, 0, 16)
+    acc2 = runtime.accumulator(p)
+    for a, b in ((0, 3), (3, 9), (9, 16)):
+        p.contract_slices(ws, acc2, a, b)
+    acc3 = runtime.accumulator(p)
+    p.contract_slice_list(ws, acc3, [5, 0, 15, 1, 2, 3, 4, 6, 7, 8, 9, 10, 11, 12, 13, 14])
+    torch.cuda.synchronize()
+    a1, a2, a3 = (x.cpu().numpy() for x in (acc1, acc2, acc3))
+    np.testing.assert_allclose(a2, a1, rtol=0, atol=1e-15 * np.abs(a1).max())
+    np.testing.assert_array_equal(a3, a1)
+
+
+def test_determinism_bitwise():
+    w = rqc.workload("c2_5x5_m16")
+    p = _plan(w, n_slice_edges=8, restarts=2)
+    _say("c2 determinism")
+    a = _run(p)
+    b = _run(p)
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("n_open", [0, 12])
+def test_degenerate_open_counts(n_open):
+    c = rqc.random_circuit(rqc.rect_layout(3, 4), 8, seed=7)
+    rng = np.random.default_rng(n_open)
+    open_q = sorted(rng.choice(12, size=n_open, replace=False).tolist())
+    fixed_q = [q for q in range(12) if q not in open_q]
+    bits = rng.integers(0, 2, size=len(fixed_q)).astype(np.uint8)
+    from paper_2103_03074_amd import tn
+    _say("open count", n_open)
+    p = tn.Plan(c, open_q, fixed_q, bits, n_slice_edges=1)
+    got = _run(p)
+    ref = sv.amplitudes_from_state(sv.simulate_numpy(c), 12, open_q, fixed_q, bits)
+    assert _rel(got, ref) < C64_TOL
+
+
+def test_gate_less_qubit_and_no_slicing():
+    c = rqc.random_circuit(rqc.rect_layout(1, 3), 1, seed=1)
+    from paper_2103_03074_amd import tn
+    psi = sv.simulate_numpy(c)
+    for open_q in ([0, 2], [1], []):
+        fixed_q = [q for q in range(3) if q not in open_q]
+        bits = [1] * len(fixed_q)
+        _say("gate-less qubit, open", open_q)
+        p = tn.Plan(c, open_q, fixed_q, bits, n_slice_edges=0)
+        got = _run(p)
+        ref = sv.amplitudes_from_state(psi, 3, open_q, fixed_q, np.array(bits, dtype=np.uint8))
+        assert _rel(got, ref) < C64_TOL
+
+
+def test_product_circuit_closed_form_per_slice():
+    lay = rqc.rect_layout(4, 5)
+    c = rqc.product_circuit(lay, 12, seed=3)
+    open_q = rqc.choose_open_qubits(lay, 8)
+    fixed_q = [q for q in range(20) if q not in open_q]
+    bits = rqc.fixed_bits(len(fixed_q), seed=1)
+    from paper_2103_03074_amd import tn
+    p = tn.Plan(c, open_q, fixed_q, bits, n_slice_edges=6, restarts=2)
+    sliced = p.sliced_edges()
+    for j in (0, 17, 63):
+        _say("product circuit slice", j)
+        got = _run(p, (j, j + 1))
+        ref = cf.product_amplitudes(c, open_q, fixed_q, bits, sliced, j)
+        assert _rel(got, ref) < C64_TOL
+
+
+def test_xeb_on_device_matches_oracle(c2_state):
+    torch = _torch()
+    from paper_2103_03074_amd import tn
+    w, psi = c2_state
+    ref = sv.amplitudes_from_state(psi, 25, w["open_q"], w["fixed_q"], w["bits"])
+    d = torch.from_numpy(np.ascontiguousarray(ref).view(np.float64)).cuda()
+    ks = [1, 10, 100, 1024]
+    _say("xeb device")
+    r = tn.xeb(d, 10, 25, 1.0, ks)
+    p = stats.probabilities(ref)
+    assert r["F_unif"] == pytest.approx(stats.xeb(p, 25), rel=1e-12, abs=1e-12)
+    assert r["F_self"] == pytest.approx(stats.xeb_self(p, 25), rel=1e-12)
+    assert r["P_s1"] == pytest.approx(stats.marginal(p), rel=1e-12)
+    assert abs(r["cond_xeb"]) < 1e-12
+    np.testing.assert_allclose(r["topk"], stats.topk_curve(p, 25, ks), rtol=1e-12)
+    assert r["p_max"] == pytest.approx(p.max(), rel=1e-14)
