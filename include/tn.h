@@ -58,9 +58,10 @@ typedef enum {
 typedef enum {
     TN_C64 = 0,        /* complex64 storage, FP32 MFMA (the paper's precision) */
     TN_C128 = 1,       /* complex128 storage and arithmetic (FP64 recontraction) */
-    TN_SPLIT_FP16 = 2, /* complex64 storage, products as hi/lo FP16 pairs on FP16 MFMA,
+    TN_SPLIT_FP16 = 2, /* complex64 storage; dense steps as hi/lo FP16 pairs on FP16 MFMA
+                          (3 products), FP32 accumulation, per-tensor power-of-two scaling */
+    TN_BF16 = 3        /* complex64 storage; dense steps on BF16 MFMA (1 product),
                           FP32 accumulation, per-tensor power-of-two scaling */
-    TN_BF16 = 3        /* BF16 complex storage, BF16 MFMA, FP32 accumulation */
 } tn_precision;
 
 /* One gate: q1 = -1 for a single-qubit gate.  Matrix row-major, row = output
@@ -199,6 +200,29 @@ tn_status tn_amplitudes(tn_plan_t p, const double* d_acc, double* d_amps,
 tn_status tn_xeb(const double* d_amps, int32_t n_open, int32_t n_qubits, double weight,
                  const int64_t* ks, int32_t n_ks, double* h_topk,
                  tn_xeb_result* out, void* hip_stream);
+
+/* Per-step timing of the slice-dependent steps, for measurement and for the
+ * learned step-time model.  While enabled, tn_contract_slices records HIP
+ * events around every step it launches (two event sets used alternately, so
+ * the host never waits on the group it has just queued) and accumulates the
+ * elapsed times. */
+typedef struct {
+    int32_t m_log, n_log, k_log, b_log;   /* step shape C[b,m,n] = sum_k A[k,b,m] B[k,b,n] */
+    int32_t kernel, tile;                 /* 0 VALU streaming, 1 MFMA tile, 2 split-K; tile id */
+    double cmacs;                         /* complex multiply-adds per launch */
+    double bytes;                         /* algorithmic bytes per launch (A + B + C) */
+    double total_ms;                      /* summed GPU time of this step's launches */
+    uint64_t launches;
+    char kernel_name[48];                 /* device function name as profilers show it */
+} tn_step_profile;
+
+/* Enable (1) or disable (0) step timing; enabling resets the counters. */
+tn_status tn_plan_set_profiling(tn_plan_t p, int32_t enable);
+
+/* Read the counters (synchronises outstanding timed work).  Entry i is the
+ * i-th slice-dependent step in execution order; the last entry is the float64
+ * slice sum.  *n receives the number of entries (<= cap are written). */
+tn_status tn_plan_step_profile(tn_plan_t p, tn_step_profile* out, int32_t cap, int32_t* n);
 
 /* Release a plan and its device memory (NULL is ignored). */
 void tn_plan_destroy(tn_plan_t p);

@@ -51,8 +51,6 @@ tn_status tn_plan(const tn_circuit* c, const int32_t* open_q, int32_t n_open, co
         std::vector<int> o(open_q, open_q + n_open), f(fixed_q, fixed_q + n_fixed);
         std::vector<uint8_t> b(fixed_bits, fixed_bits + n_fixed);
         tn_plan_opts op = opts ? *opts : tn::default_opts();
-        if (op.prec == TN_BF16 || op.prec == TN_SPLIT_FP16)
-            return fail(TN_EUNSUPPORTED, "precision not available in this build");
         auto* h = new tn_plan_s;
         std::string err = tn::make_plan(*c, o, f, b, tree, sliced, n_sliced, op, h->plan);
         if (!err.empty()) {
@@ -250,6 +248,53 @@ tn_status tn_xeb(const double* d_amps, int32_t n_open, int32_t n_qubits, double 
         }
     }
     return done(TN_OK);
+}
+
+tn_status tn_plan_set_profiling(tn_plan_t p, int32_t enable) {
+    if (!p) return fail(TN_EINVAL, "plan is NULL");
+    return from_err(tn::profile_enable(p->plan, p->dev, enable != 0));
+}
+
+tn_status tn_plan_step_profile(tn_plan_t p, tn_step_profile* out, int32_t cap, int32_t* n) {
+    if (!p || !n || (cap > 0 && !out)) return fail(TN_EINVAL, "NULL argument");
+    tn::Profiler& pf = p->dev.prof;
+    std::string e = tn::profile_harvest(p->dev);
+    if (!e.empty()) return fail(TN_EDEVICE, e);
+    *n = (int32_t)pf.ms.size();
+    int di = 0;
+    for (const tn::Step& st : p->plan.steps) {
+        if (st.invariant) continue;
+        if (di < cap) {
+            tn_step_profile& o = out[di];
+            std::memset(&o, 0, sizeof(o));
+            o.m_log = st.m_log;
+            o.n_log = st.n_log;
+            o.k_log = st.k_log;
+            o.b_log = st.b_log;
+            o.kernel = st.kernel;
+            o.tile = st.tile;
+            o.cmacs = st.cmacs;
+            o.bytes = st.bytes;
+            o.total_ms = di < (int)pf.ms.size() ? pf.ms[di] : 0.0;
+            o.launches = di < (int)pf.launches.size() ? pf.launches[di] : 0;
+            if (di < (int)pf.names.size()) std::strncpy(o.kernel_name, pf.names[di].c_str(), sizeof(o.kernel_name) - 1);
+        }
+        ++di;
+    }
+    if (di < cap && di < (int)pf.ms.size()) {   // slice sum
+        tn_step_profile& o = out[di];
+        std::memset(&o, 0, sizeof(o));
+        o.m_log = p->plan.root_log2;
+        o.b_log = p->plan.batch_log2;
+        o.kernel = -1;
+        o.cmacs = 0;
+        o.bytes = (double)p->plan.esize * std::ldexp(1.0, p->plan.root_log2 + p->plan.batch_log2) +
+                  32.0 * std::ldexp(1.0, p->plan.root_log2);
+        o.total_ms = pf.ms[di];
+        o.launches = pf.launches[di];
+        std::strncpy(o.kernel_name, pf.names[di].c_str(), sizeof(o.kernel_name) - 1);
+    }
+    return TN_OK;
 }
 
 void tn_plan_destroy(tn_plan_t p) {

@@ -53,13 +53,27 @@ void* node_ptr(const Plan& p, const DeviceState& d, void* ws, int node, uint64_t
     return base + off * (uint64_t)p.esize;
 }
 
-std::string launch_step(const Plan& p, const Step& st, const void* A, const void* B, void* C, void* ws,
-                        hipStream_t s) {
+int lp_mode(tn_precision p) {
+    switch (p) {
+        case TN_SPLIT_FP16: return LP_SPLIT_FP16;
+        case TN_BF16: return LP_BF16;
+        default: return -1;
+    }
+}
+
+std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, const void* A, const void* B, void* C,
+                        void* ws, hipStream_t s, std::string* name = nullptr) {
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
     g.A = A;
     g.B = B;
     g.C = C;
+    if (d.d_max) {
+        g.amax = d.d_max + p.nodes[st.a_node].slot;
+        g.bmax = d.d_max + p.nodes[st.b_node].slot;
+        g.cmax = d.d_max + p.nodes[st.node].slot;
+    }
+    const int mode = lp_mode(p.opts.prec);
     g.m_log = st.m_log;
     g.n_log = st.n_log;
     g.k_log = st.k_log;
@@ -101,9 +115,18 @@ std::string launch_step(const Plan& p, const Step& st, const void* A, const void
         g.ep_pos[i] = (uint8_t)ep[i].first;
         g.ep_src[i] = (uint8_t)ep[i].second;
     }
+    if (name) {
+        static const char* tile_names[] = {"<4,4,2,2", "<2,2,2,2", "<2,2,4,1", "<1,1,4,1", "<4,1,4,1"};
+        static const char* mode_names[] = {",0>", ",1>", ",2>"};
+        if (st.kernel == K_MFMA)
+            *name = mode < 0 ? std::string("k_mfma_c64") + tile_names[st.tile] + ">"
+                             : std::string("k_mfma_lp") + tile_names[st.tile] + mode_names[mode];
+        else *name = std::string("k_valu<") + (storage == ST_C128 ? "double2," : "float2,") + std::to_string(R) +
+                     ">" + (g.split_log > 0 ? "+k_splitk_red" : "");
+    }
     hipError_t e;
     if (st.kernel == K_MFMA) {
-        e = launch_mfma(0, st.tile, g, s);
+        e = launch_mfma(mode, st.tile, g, s);
     } else {
         e = launch_valu(storage, g, R, s);
         if (e == hipSuccess && g.split_log > 0) e = launch_splitk_reduce(storage, g, s);
@@ -112,13 +135,57 @@ std::string launch_step(const Plan& p, const Step& st, const void* A, const void
     return "";
 }
 
+std::string profile_harvest_set(DeviceState& d, int set) {
+    Profiler& pf = d.prof;
+    if (!pf.pending[set]) return "";
+    const int n = (int)pf.ms.size();
+    TN_HIP(hipEventSynchronize(pf.ev[set][n]));
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.f;
+        TN_HIP(hipEventElapsedTime(&ms, pf.ev[set][i], pf.ev[set][i + 1]));
+        pf.ms[i] += ms;
+        pf.launches[i] += 1;
+    }
+    pf.pending[set] = false;
+    return "";
+}
+
 }  // namespace
+
+std::string profile_harvest(DeviceState& d) {
+    std::string e = profile_harvest_set(d, 0);
+    if (!e.empty()) return e;
+    return profile_harvest_set(d, 1);
+}
+
+std::string profile_enable(Plan& p, DeviceState& d, bool on) {
+    Profiler& pf = d.prof;
+    if (pf.on) {
+        std::string e = profile_harvest(d);
+        if (!e.empty()) return e;
+    }
+    const int n = (int)p.steps.size() - p.n_invariant_steps + 1;
+    if (on) {
+        for (int set = 0; set < 2; ++set) {
+            if ((int)pf.ev[set].size() != n + 1) {
+                for (auto ev : pf.ev[set]) (void)hipEventDestroy(ev);
+                pf.ev[set].assign(n + 1, nullptr);
+                for (auto& ev : pf.ev[set]) TN_HIP(hipEventCreate(&ev));
+            }
+            pf.pending[set] = false;
+        }
+        pf.ms.assign(n, 0.0);
+        pf.launches.assign(n, 0);
+        pf.names.assign(n, std::string());
+    }
+    pf.on = on;
+    return "";
+}
 
 int storage_of(tn_precision p) {
     switch (p) {
         case TN_C128: return ST_C128;
-        case TN_BF16: return ST_BF16;
-        default: return ST_C64;
+        default: return ST_C64;   // split-FP16 and BF16 keep complex64 storage
     }
 }
 
@@ -128,7 +195,6 @@ std::string prepare(Plan& p, DeviceState& d, hipStream_t s) {
     if (d.prepared && d.device == dev) return "";
     if (d.prepared && d.device != dev) return "plan was prepared on another device";
     const int storage = storage_of(p.opts.prec);
-    if (storage == ST_BF16) return "bf16 storage is not available in this build";
     d.device = dev;
     d.plan_bytes = std::max<uint64_t>(p.plan_elems, 64) * (uint64_t)p.esize;
     TN_HIP(hipMalloc(&d.plan_mem, d.plan_bytes));
@@ -136,13 +202,25 @@ std::string prepare(Plan& p, DeviceState& d, hipStream_t s) {
     for (int i = 0; i < p.tree.n_leaves; ++i)
         put_leaf(p.net.leaves[i], p.nodes[i].layout, storage, host.data() + p.nodes[i].off * p.esize);
     TN_HIP(hipMemcpy(d.plan_mem, host.data(), d.plan_bytes, hipMemcpyHostToDevice));
+    if (lp_mode(p.opts.prec) >= 0) {
+        // max-magnitude slots: leaves from the host data, the rest zero
+        const int n_slots = (int)p.tree.n_nodes();
+        std::vector<float> h(n_slots, 0.f);
+        for (int i = 0; i < p.tree.n_leaves; ++i) {
+            double m = 0;
+            for (const cd& v : p.net.leaves[i].data) m = std::max(m, std::max(std::abs(v.real()), std::abs(v.imag())));
+            h[p.nodes[i].slot] = (float)m;
+        }
+        TN_HIP(hipMalloc(&d.d_max, sizeof(float) * n_slots));
+        TN_HIP(hipMemcpy(d.d_max, h.data(), sizeof(float) * n_slots, hipMemcpyHostToDevice));
+    }
     for (const Step& st : p.steps) {
         if (!st.invariant) continue;
         void* A = node_ptr(p, d, nullptr, st.a_node, 0);
         void* B = node_ptr(p, d, nullptr, st.b_node, 0);
         void* C = (unsigned char*)d.plan_mem + st.c_off * (uint64_t)p.esize;
         if (st.kernel == K_SPLITK) return "split-K step in the slice-invariant part needs a workspace";
-        std::string err = launch_step(p, st, A, B, C, nullptr, s);
+        std::string err = launch_step(p, d, st, A, B, C, nullptr, s);
         if (!err.empty()) return err;
     }
     d.mask_words = std::max<size_t>(1, ((size_t(1) << p.batch_log2) + 31) / 32);
@@ -171,15 +249,41 @@ std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std
         TN_HIP(hipStreamSynchronize(s));
     }
     std::string err;
+    Profiler& pf = d.prof;
+    const int n_dep = (int)p.steps.size() - p.n_invariant_steps;
+    if (pf.on && pf.ms.size() != (size_t)n_dep + 1) return "profiler not sized for this plan";
     for (size_t gi = 0; gi < groups.size() && err.empty(); ++gi) {
         const Group& G = groups[gi];
+        const int set = (int)(gi & 1);
+        if (pf.on) {
+            if (pf.pending[set]) {   // harvest the group queued two groups ago
+                err = profile_harvest_set(d, set);
+                if (!err.empty()) break;
+            }
+            TN_HIP(hipEventRecord(pf.ev[set][0], s));
+        }
+        if (d.d_max) {   // reset the max slots of this group's tensors
+            const int n_slots = p.tree.n_nodes();
+            hipError_t e = launch_fill(d.d_max + p.n_static_slots, (uint64_t)(n_slots - p.n_static_slots), s);
+            if (e != hipSuccess) {
+                err = std::string("fill: ") + hipGetErrorString(e);
+                break;
+            }
+        }
+        int di = 0;
         for (const Step& st : p.steps) {
             if (st.invariant) continue;
             void* A = node_ptr(p, d, ws, st.a_node, G.slice_base);
             void* B = node_ptr(p, d, ws, st.b_node, G.slice_base);
             void* C = (unsigned char*)ws + st.c_off * (uint64_t)p.esize;
-            err = launch_step(p, st, A, B, C, ws, s);
+            std::string nm;
+            err = launch_step(p, d, st, A, B, C, ws, s, pf.on && pf.names[di].empty() ? &nm : nullptr);
             if (!err.empty()) break;
+            if (pf.on) {
+                if (!nm.empty()) pf.names[di] = nm;
+                TN_HIP(hipEventRecord(pf.ev[set][di + 1], s));
+            }
+            ++di;
         }
         if (!err.empty()) break;
         const void* rp = node_ptr(p, d, ws, root, G.slice_base);
@@ -188,6 +292,11 @@ std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std
         const uint64_t b1 = mk ? (1ull << p.batch_log2) : G.beta1;
         hipError_t e = launch_slice_sum(storage, rp, acc, p.root_log2, p.batch_log2, mk, b0, b1, s);
         if (e != hipSuccess) err = std::string("slice sum: ") + hipGetErrorString(e);
+        if (pf.on && err.empty()) {
+            if (pf.names[n_dep].empty()) pf.names[n_dep] = storage == ST_C128 ? "k_slice_sum<double2>" : "k_slice_sum<float2>";
+            TN_HIP(hipEventRecord(pf.ev[set][n_dep + 1], s));
+            pf.pending[set] = true;
+        }
     }
     if (d_masks) {
         hipError_t e = hipFreeAsync(d_masks, s);
@@ -197,9 +306,12 @@ std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std
 }
 
 void release(DeviceState& d) {
+    for (int set = 0; set < 2; ++set)
+        for (auto ev : d.prof.ev[set]) (void)hipEventDestroy(ev);
     if (d.plan_mem) (void)hipFree(d.plan_mem);
     if (d.d_mask) (void)hipFree(d.d_mask);
     if (d.d_part) (void)hipFree(d.d_part);
+    if (d.d_max) (void)hipFree(d.d_max);
     d = DeviceState();
 }
 

@@ -11,6 +11,15 @@
 
 namespace tn {
 
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> ev[2];      // per group parity: one event before each step + one at the end
+    bool pending[2] = {false, false};
+    std::vector<double> ms;             // per dependent step (+ slice sum)
+    std::vector<uint64_t> launches;
+    std::vector<std::string> names;
+};
+
 struct DeviceState {
     int device = -1;
     void* plan_mem = nullptr;     // leaves + slice-invariant tensors
@@ -19,6 +28,8 @@ struct DeviceState {
     uint32_t* d_mask = nullptr;   // batch-slot masks for slice lists
     size_t mask_words = 0;
     double* d_part = nullptr;     // XEB partials
+    float* d_max = nullptr;       // per-tensor max |re|,|im| (low-precision MFMA scaling)
+    Profiler prof;
 };
 
 struct Group {
@@ -31,6 +42,8 @@ std::string prepare(Plan& p, DeviceState& d, hipStream_t s);
 std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std::vector<Group>& groups,
                        hipStream_t s);
 void release(DeviceState& d);
+std::string profile_enable(Plan& p, DeviceState& d, bool on);
+std::string profile_harvest(DeviceState& d);
 
 int storage_of(tn_precision p);
 

@@ -52,6 +52,16 @@ __device__ __forceinline__ uint64_t deposit(uint64_t x, const uint8_t* pos, int 
     return r;
 }
 
+__device__ __forceinline__ float cabsmax(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
+__device__ __forceinline__ float cabsmax(double2 v) { return (float)fmax(fabs(v.x), fabs(v.y)); }
+
+// Largest |re|, |im| of a tile into *slot: one vector atomic per wave (the
+// bit pattern of a non-negative float orders like an unsigned integer).
+__device__ __forceinline__ void tile_max_atomic(float v, float* slot) {
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int*>(slot), __float_as_uint(v));
+}
+
 struct TileIndex {
     uint64_t m0, n0, beta, split;
 };
@@ -145,6 +155,13 @@ __global__ void __launch_bounds__(256) k_valu(GemmArgs g) {
         }
         return;
     }
+    if (g.cmax) {
+        float mx = 0.f;
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (tid + 256 * j < ntile) mx = fmaxf(mx, cabsmax(acc[j]));
+        tile_max_atomic(mx, g.cmax);
+    }
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int o = tid + 256 * j;
@@ -166,10 +183,12 @@ __global__ void __launch_bounds__(256) k_splitk_red(GemmArgs g) {
     const int lt = g.m_log + g.n_log + g.b_log;
     const uint64_t total = 1ull << lt;
     const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= total) return;
     const T* P = reinterpret_cast<const T*>(g.scratch);
     T s = czero<T>();
-    for (uint64_t sp = 0; sp < (1ull << g.split_log); ++sp) s = cadd(s, P[(sp << lt) + i]);
+    if (i < total)
+        for (uint64_t sp = 0; sp < (1ull << g.split_log); ++sp) s = cadd(s, P[(sp << lt) + i]);
+    if (g.cmax) tile_max_atomic(cabsmax(s), g.cmax);
+    if (i >= total) return;
     const uint64_t m = i & ((1ull << g.m_log) - 1);
     const uint64_t n = (i >> g.m_log) & ((1ull << g.n_log) - 1);
     const uint64_t be = i >> (g.m_log + g.n_log);
@@ -250,6 +269,16 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
                            deposit(ti.beta, g.cpb, 0, g.b_log);
     float2* C = reinterpret_cast<float2*>(g.C) + cbase;
     const float2* Cs = reinterpret_cast<const float2*>(smem);
+    if (g.cmax) {
+        float mx = 0.f;
+#pragma unroll
+        for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) mx = fmaxf(mx, fabsf(acc[bm][bn][r]));
+        tile_max_atomic(mx, g.cmax);
+    }
     for (int p0 = 0; p0 < TM; p0 += RP) {
 #pragma unroll
         for (int bm = 0; bm < WM; ++bm)
@@ -271,6 +300,200 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
         }
         __syncthreads();
     }
+}
+
+// ------------------------------------------------- low-precision MFMA
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// pack two reals (re in the low half) after scaling
+template <int MODE>
+__device__ __forceinline__ void split_pack(float2 v, uint32_t& hi, uint32_t& lo) {
+    if constexpr (MODE == LP_BF16) {
+        const __bf16 r = (__bf16)v.x, i = (__bf16)v.y;
+        hi = (uint32_t)__builtin_bit_cast(uint16_t, r) | ((uint32_t)__builtin_bit_cast(uint16_t, i) << 16);
+        lo = 0;
+    } else {
+        const _Float16 r = (_Float16)v.x, i = (_Float16)v.y;
+        hi = (uint32_t)__builtin_bit_cast(uint16_t, r) | ((uint32_t)__builtin_bit_cast(uint16_t, i) << 16);
+        if constexpr (MODE == LP_SPLIT_FP16) {
+            // remainder scaled by 2^11 so it stays normal in FP16
+            const _Float16 lr = (_Float16)((v.x - (float)r) * 2048.f);
+            const _Float16 li = (_Float16)((v.y - (float)i) * 2048.f);
+            lo = (uint32_t)__builtin_bit_cast(uint16_t, lr) | ((uint32_t)__builtin_bit_cast(uint16_t, li) << 16);
+        } else {
+            lo = 0;
+        }
+    }
+}
+
+// B column of the real expansion: even real column (re part of C) takes
+// (re, -im) pairs, odd real column (im part) takes (im, re) pairs.
+__device__ __forceinline__ uint32_t bexp(uint32_t w, int odd) {
+    return odd ? ((w >> 16) | (w << 16)) : (w ^ 0x80000000u);
+}
+
+__device__ __forceinline__ int scale_exp(const float* mx) {
+    const float m = mx ? *mx : 0.f;
+    return m > 0.f ? ilogbf(m) + 1 : 0;   // m * 2^-e in [0.5, 1)
+}
+
+// Complex GEMM on FP16 / BF16 MFMA (v_mfma_f32_16x16x32_{f16,bf16}) with
+// FP32 accumulation.  Operands are scaled by a power of two taken from the
+// producers' max (exact, so nothing underflows FP16) and split into hi/lo
+// FP16 pairs: x = hi + 2^-11 lo, product = hi*hi + 2^-11 (hi*lo + lo*hi)
+// (split mode; the single-term modes use hi only).  The complex product is
+// 4 real products as in the FP32 kernel: A' = [Re A | Im A] interleaved,
+// B expanded to [[re, im], [-im, re]] while the fragment is built.
+template <int WM, int WN, int WAVES_M, int WAVES_N, int MODE>
+__global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
+    constexpr int TM = WAVES_M * WM * 16;
+    constexpr int TNR = WAVES_N * WN * 16;
+    constexpr int TN = TNR / 2;
+    constexpr int TK = 16;                  // complex k per chunk = one MFMA k-step (32 real)
+    constexpr int LD = TK + 4;              // packed (re, im) words per LDS row, padded
+    constexpr bool SPLIT = MODE == LP_SPLIT_FP16;
+    constexpr int PLANES = SPLIT ? 2 : 1;
+    constexpr int AB_WORDS = PLANES * (TM + TN) * LD;
+    constexpr int RP = (TM * TNR <= kMfmaSmemFloats) ? TM : kMfmaSmemFloats / TNR;
+    constexpr int SM_WORDS = AB_WORDS > kMfmaSmemFloats ? AB_WORDS : kMfmaSmemFloats;
+    __shared__ __attribute__((aligned(16))) uint32_t smem[SM_WORDS];
+    uint32_t* Ahi = smem;
+    uint32_t* Alo = Ahi + TM * LD;
+    uint32_t* Bhi = smem + PLANES * TM * LD;
+    uint32_t* Blo = Bhi + TN * LD;
+    const TileIndex ti = tile_index(g);
+    const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
+    const float2* A = reinterpret_cast<const float2*>(g.A) + (ti.beta << g.m_log) + ti.m0;
+    const float2* B = reinterpret_cast<const float2*>(g.B) + (ti.beta << g.n_log) + ti.n0;
+    const int ea = scale_exp(g.amax), eb = scale_exp(g.bmax);
+    const float sa = ldexpf(1.f, -ea), sb = ldexpf(1.f, -eb);
+    const uint64_t K = 1ull << g.k_log;
+    const int TKe = K < (uint64_t)TK ? (int)K : TK;
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, lane = tid & 63;
+    const int wm = w % WAVES_M, wn = w / WAVES_M;
+    const int lr = lane & 15, lg = lane >> 4;
+    floatx4 acc[WM][WN], accx[SPLIT ? WM : 1][SPLIT ? WN : 1];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (SPLIT) {
+#pragma unroll
+        for (int i = 0; i < (SPLIT ? WM : 1); ++i)
+#pragma unroll
+            for (int j = 0; j < (SPLIT ? WN : 1); ++j) accx[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (uint64_t k0 = 0; k0 < K; k0 += TK) {
+        for (int e = tid; e < TK * TM; e += 256) {
+            const int kk = e / TM, mm = e % TM;
+            uint32_t hi = 0, lo = 0;
+            if (kk < TKe) {
+                float2 v = A[(k0 + kk) * sAk + mm];
+                v.x *= sa;
+                v.y *= sa;
+                split_pack<MODE>(v, hi, lo);
+            }
+            Ahi[mm * LD + kk] = hi;
+            if constexpr (SPLIT) Alo[mm * LD + kk] = lo;
+        }
+        for (int e = tid; e < TK * TN; e += 256) {
+            const int kk = e / TN, nn = e % TN;
+            uint32_t hi = 0, lo = 0;
+            if (kk < TKe) {
+                float2 v = B[(k0 + kk) * sBk + nn];
+                v.x *= sb;
+                v.y *= sb;
+                split_pack<MODE>(v, hi, lo);
+            }
+            Bhi[nn * LD + kk] = hi;
+            if constexpr (SPLIT) Blo[nn * LD + kk] = lo;
+        }
+        __syncthreads();
+        uint4 ah[WM], al[SPLIT ? WM : 1], bh[WN], bl[SPLIT ? WN : 1];
+#pragma unroll
+        for (int bm = 0; bm < WM; ++bm) {
+            const int row = (wm * WM + bm) * 16 + lr;
+            ah[bm] = *reinterpret_cast<const uint4*>(Ahi + row * LD + 4 * lg);
+            if constexpr (SPLIT) al[bm] = *reinterpret_cast<const uint4*>(Alo + row * LD + 4 * lg);
+        }
+#pragma unroll
+        for (int bn = 0; bn < WN; ++bn) {
+            const int jr = (wn * WN + bn) * 16 + lr;
+            const int odd = jr & 1;
+            uint4 v = *reinterpret_cast<const uint4*>(Bhi + (jr >> 1) * LD + 4 * lg);
+            bh[bn] = uint4{bexp(v.x, odd), bexp(v.y, odd), bexp(v.z, odd), bexp(v.w, odd)};
+            if constexpr (SPLIT) {
+                uint4 u = *reinterpret_cast<const uint4*>(Blo + (jr >> 1) * LD + 4 * lg);
+                bl[bn] = uint4{bexp(u.x, odd), bexp(u.y, odd), bexp(u.z, odd), bexp(u.w, odd)};
+            }
+        }
+#pragma unroll
+        for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn) {
+                if constexpr (MODE == LP_BF16) {
+                    acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bh[bn]), acc[bm][bn], 0, 0, 0);
+                } else {
+                    acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                        __builtin_bit_cast(half8, ah[bm]), __builtin_bit_cast(half8, bh[bn]), acc[bm][bn], 0, 0, 0);
+                    if constexpr (SPLIT) {
+                        accx[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                            __builtin_bit_cast(half8, ah[bm]), __builtin_bit_cast(half8, bl[bn]), accx[bm][bn], 0, 0, 0);
+                        accx[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                            __builtin_bit_cast(half8, al[bm]), __builtin_bit_cast(half8, bh[bn]), accx[bm][bn], 0, 0, 0);
+                    }
+                }
+            }
+        __syncthreads();
+    }
+    // undo the scaling exactly and fold in the cross terms
+    const float sc = ldexpf(1.f, ea + eb);
+    float mx = 0.f;
+#pragma unroll
+    for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = acc[bm][bn][r];
+                if constexpr (SPLIT) v = fmaf(accx[bm][bn][r], 1.f / 2048.f, v);
+                v *= sc;
+                acc[bm][bn][r] = v;
+                mx = fmaxf(mx, fabsf(v));
+            }
+    if (g.cmax) tile_max_atomic(mx, g.cmax);
+    const uint64_t cbase = deposit(ti.m0, g.cpm, g.tm, g.m_log) + deposit(ti.n0, g.cpn, g.tn, g.n_log) +
+                           deposit(ti.beta, g.cpb, 0, g.b_log);
+    float2* C = reinterpret_cast<float2*>(g.C) + cbase;
+    float* fs = reinterpret_cast<float*>(smem);
+    const float2* Cs = reinterpret_cast<const float2*>(smem);
+    for (int p0 = 0; p0 < TM; p0 += RP) {
+#pragma unroll
+        for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = (wm * WM + bm) * 16 + 4 * lg + r;
+                    if (i >= p0 && i < p0 + RP) fs[(i - p0) * TNR + (wn * WN + bn) * 16 + lr] = acc[bm][bn][r];
+                }
+        __syncthreads();
+        for (int x = tid; x < TM * TN; x += 256) {
+            int ml, nl;
+            const uint64_t off = decode_ep(g, x, ml, nl);
+            if (ml >= p0 && ml < p0 + RP) C[off] = Cs[(ml - p0) * TN + nl];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fill(float* p, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.f;
 }
 
 // ------------------------------------------------------------ slice sum
@@ -402,9 +625,29 @@ hipError_t launch_splitk_reduce(int storage, const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int MODE>
+static hipError_t launch_lp(int tile, const GemmArgs& g, dim3 grid, hipStream_t s) {
+    switch (tile) {
+        case 0: hipLaunchKernelGGL((k_mfma_lp<4, 4, 2, 2, MODE>), grid, dim3(256), 0, s, g); break;
+        case 1: hipLaunchKernelGGL((k_mfma_lp<2, 2, 2, 2, MODE>), grid, dim3(256), 0, s, g); break;
+        case 2: hipLaunchKernelGGL((k_mfma_lp<2, 2, 4, 1, MODE>), grid, dim3(256), 0, s, g); break;
+        case 3: hipLaunchKernelGGL((k_mfma_lp<1, 1, 4, 1, MODE>), grid, dim3(256), 0, s, g); break;
+        case 4: hipLaunchKernelGGL((k_mfma_lp<4, 1, 4, 1, MODE>), grid, dim3(256), 0, s, g); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, uint64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, grid_for((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_mfma(int mode, int tile, const GemmArgs& g, hipStream_t s) {
-    (void)mode;
     const dim3 grid = grid_for(tile_blocks(g));
+    if (mode == LP_SPLIT_FP16) return launch_lp<LP_SPLIT_FP16>(tile, g, grid, s);
+    if (mode == LP_FP16) return launch_lp<LP_FP16>(tile, g, grid, s);
+    if (mode == LP_BF16) return launch_lp<LP_BF16>(tile, g, grid, s);
     switch (tile) {
         case 0: hipLaunchKernelGGL((k_mfma_c64<4, 4, 2, 2>), grid, dim3(256), 0, s, g); break;
         case 1: hipLaunchKernelGGL((k_mfma_c64<2, 2, 2, 2>), grid, dim3(256), 0, s, g); break;

@@ -25,16 +25,21 @@ struct GemmArgs {
     uint8_t ep_pos[16];     // address bit of the i-th lowest tile bit of C
     uint8_t ep_src[16];     // logical source: < 32 -> m bit, >= 32 -> n bit (src - 32)
     uint8_t cpm[kMaxBits], cpn[kMaxBits], cpb[kMaxBits];
-    int scale_a, scale_b;   // power-of-two exponents applied on load (mixed precision)
-    int scale_c;            // exponent applied on store
+    const float* amax;      // max |re|,|im| of A and B (low-precision MFMA scaling), or null
+    const float* bmax;
+    float* cmax;            // producer epilogue: atomic max of |re|,|im| of C, or null
 };
+
+// low-precision MFMA modes
+enum LpMode : int { LP_SPLIT_FP16 = 0, LP_FP16 = 1, LP_BF16 = 2 };
 
 // storage kinds
 enum Storage : int { ST_C64 = 0, ST_C128 = 1, ST_BF16 = 2 };
 
 hipError_t launch_valu(int storage, const GemmArgs& g, int R, hipStream_t s);
 hipError_t launch_splitk_reduce(int storage, const GemmArgs& g, hipStream_t s);
-hipError_t launch_mfma(int mode, int tile, const GemmArgs& g, hipStream_t s);
+hipError_t launch_mfma(int mode, int tile, const GemmArgs& g, hipStream_t s);   // mode -1: FP32, else LpMode
+hipError_t launch_fill(float* p, uint64_t n, hipStream_t s);
 hipError_t launch_slice_sum(int storage, const void* root, double* acc, int res_log, int b_log,
                             const uint32_t* d_mask, uint64_t beta0, uint64_t beta1, hipStream_t s);
 hipError_t launch_copy_acc(const double* src, double* dst, uint64_t n, hipStream_t s);

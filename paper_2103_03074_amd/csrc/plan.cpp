@@ -15,6 +15,8 @@
 #include <random>
 #include <set>
 #include <sstream>
+#include <cstdio>
+#include <cstdlib>
 
 #include "plan.hpp"
 #include "tiles.hpp"
@@ -283,8 +285,7 @@ BatchShape batch_shape(const TreeLegs& tl, const Tree& t, const std::vector<char
 int storage_bytes(tn_precision p) {
     switch (p) {
         case TN_C128: return 16;
-        case TN_BF16: return 4;
-        default: return 8;
+        default: return 8;   // complex64 storage (also for the FP16/BF16 MFMA modes)
     }
 }
 
@@ -490,6 +491,16 @@ static std::string finalize(Plan& p) {
             plan_top += Arena::round(uint64_t(1) << p.nodes[st.node].legs.size());
         }
     p.plan_elems = plan_top;
+    // max-magnitude slots: leaves, then invariant tensors, then dependent ones
+    {
+        int next = 0;
+        for (int i = 0; i < t.n_leaves; ++i) p.nodes[i].slot = next++;
+        for (auto& st : p.steps)
+            if (st.invariant) p.nodes[st.node].slot = next++;
+        p.n_static_slots = next;
+        for (auto& st : p.steps)
+            if (!st.invariant) p.nodes[st.node].slot = next++;
+    }
     Arena ws;
     for (auto& st : p.steps) {
         if (st.invariant) continue;
@@ -607,13 +618,24 @@ std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
         }
         cands.push_back(t);
     } else {
+        // candidates alternate between hierarchical bipartition (appendix A)
+        // and randomised greedy orders; the cheapest after slicing is kept
         const int R = std::max(1, opts.restarts);
         std::mt19937_64 rng(opts.seed + 777);
-        std::uniform_real_distribution<double> ua(0.5, 1.5), ut(0.0, 1.0);
+        std::uniform_real_distribution<double> ua(0.5, 1.5), ut(0.0, 1.0), ue(0.05, 0.7);
+        std::uniform_int_distribution<int> ul(3, 16);
+        cands.push_back(time_order_tree(L));
         for (int r = 0; r < R; ++r) {
-            double alpha = r == 0 ? 1.0 : ua(rng);
-            double temp = r == 0 ? 0.0 : ut(rng);
-            cands.push_back(greedy_tree(leaf_legs, opts.seed * 1000003ULL + r, alpha, temp));
+            if (r % 4 == 2) {
+                const double eps = r == 0 ? 0.3 : ue(rng);
+                const int leaf = r == 0 ? 8 : ul(rng);
+                const int open_w = r == 0 ? 2 : (int)(rng() % 4);
+                cands.push_back(partition_tree(leaf_legs, opts.seed * 1000003ULL + r, eps, leaf, open_w));
+            } else {
+                double alpha = r == 1 ? 1.0 : ua(rng);
+                double temp = r == 1 ? 0.0 : ut(rng);
+                cands.push_back(greedy_tree(leaf_legs, opts.seed * 1000003ULL + r, alpha, temp));
+            }
         }
     }
     if (L == 1) {
@@ -626,13 +648,39 @@ std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
     double best_cost = -1;
     const int n_force = fixed_slicing ? 0 : std::max(0, opts.n_slice_edges);
     for (auto& t : cands) {
+        std::vector<char> in_s(E, 0);
+        if (!tree) {   // local optimisation of the unsliced tree
+            if (fixed_slicing)
+                for (int e : user_sliced) in_s[e] = 1;
+            t = reconfigure(leaf_legs, t, in_s, fixed_slicing ? opts.max_log2_size : 64, 8, 16);
+        }
         TreeLegs tl = tree_legs(net, t);
         std::vector<int> s = fixed_slicing ? user_sliced
                                            : greedy_slice(net, t, tl, opts.max_log2_size, n_force, {});
-        std::vector<char> in_s(E, 0);
         for (int e : s) in_s[e] = 1;
+        if (!tree && !fixed_slicing && !s.empty()) {
+            // re-tune the tree for one slice, then top up the slicing if needed
+            Tree t2 = reconfigure(leaf_legs, t, in_s, opts.max_log2_size, 8, 16);
+            TreeLegs tl2 = tree_legs(net, t2);
+            std::vector<int> s2 = greedy_slice(net, t2, tl2, opts.max_log2_size, n_force, s);
+            std::vector<char> in2(E, 0);
+            for (int e : s2) in2[e] = 1;
+            if (slice_cost_tl(tl2, t2, in2).total((int)s2.size()) <
+                slice_cost_tl(tl, t, in_s).total((int)s.size())) {
+                t = t2;
+                tl = tl2;
+                s = s2;
+                in_s = in2;
+            }
+        }
         SliceCost sc = slice_cost_tl(tl, t, in_s);
         double cost = sc.total((int)s.size());
+        if (std::getenv("TN_DEBUG_CANDS")) {
+            std::vector<char> none(E, 0);
+            SliceCost raw = slice_cost_tl(tl, t, none);
+            std::fprintf(stderr, "cand %zu: raw max %d log2 %.2f | k %zu log2 total %.2f\n",
+                         (size_t)(&t - &cands[0]), raw.max_log2, std::log2(raw.invariant), s.size(), std::log2(cost));
+        }
         if (best_cost < 0 || cost < best_cost) {
             best_cost = cost;
             out.tree = t;
@@ -650,7 +698,7 @@ std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
                                                           : (uint64_t(32) << 30);
         int want = opts.batch_log2;
         SliceCost sc = slice_cost_tl(tl, out.tree, in_s);
-        const int size_cap = std::max(sc.max_log2, 25);
+        const int size_cap = std::max(sc.max_log2, 28);
         std::vector<int> chosen;
         while ((int)chosen.size() < k) {
             if (want >= 0 && (int)chosen.size() >= want) break;

@@ -64,6 +64,20 @@ struct Tree {
 // Randomised greedy order over the given leaves' legs.
 Tree greedy_tree(const std::vector<Legs>& leaf_legs, uint64_t seed, double alpha, double temperature);
 
+// Order from recursive min-cut bisection (leaf groups of <= leaf_size tensors
+// contracted greedily); eps is the allowed size imbalance of each bisection.
+Tree partition_tree(const std::vector<Legs>& leaf_legs, uint64_t seed, double eps, int leaf_size,
+                    int open_w);
+
+// Subtree reconfiguration: repeatedly replace subtrees of up to max_frontier
+// frontier tensors by their optimal order (cost per slice with the edges in
+// in_s removed, intermediates above 2^target penalised).
+Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::vector<char>& in_s, int target,
+                 int max_frontier, int passes);
+
+// Leaves contracted one after another in network (time) order.
+Tree time_order_tree(int n_leaves);
+
 // Kernel classes a step can run on.
 enum StepKernel : int32_t { K_SMALL = 0, K_MFMA = 1, K_SPLITK = 2 };
 
@@ -96,6 +110,7 @@ struct NodeInfo {
     std::vector<int> sliced_bits;  // leaves: slice-bit index of each outer-sliced leg on top
     bool dep = false;         // depends on the slice id
     int home = HOME_WS;
+    int slot = 0;             // index of this tensor's max-magnitude slot (low-precision scaling)
     uint64_t off = 0;         // offset in its arena (elements)
     int parent = -1;
 };
@@ -114,6 +129,7 @@ struct Plan {
     uint64_t ws_elems = 0;          // per-batch workspace (elements), incl. split-K scratch
     uint64_t plan_elems = 0;        // plan-owned device memory (leaves + invariants)
     int root_log2 = 0;              // result legs of the root (without batch legs)
+    int n_static_slots = 0;         // slots of leaves and invariant tensors come first
     tn_plan_stats stats{};
     double unmerged_cmacs_per_slice = 0;
 };

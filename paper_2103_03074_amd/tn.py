@@ -78,6 +78,18 @@ class XebResult(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class StepProfile(ctypes.Structure):
+    _fields_ = [("m_log", ctypes.c_int32), ("n_log", ctypes.c_int32), ("k_log", ctypes.c_int32),
+                ("b_log", ctypes.c_int32), ("kernel", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("cmacs", ctypes.c_double), ("bytes", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("launches", ctypes.c_uint64), ("kernel_name", ctypes.c_char * 48)]
+
+    def to_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["kernel_name"] = self.kernel_name.decode()
+        return d
+
+
 # every symbol tn.h declares, with its ctypes signature
 _P = ctypes.c_void_p
 _SIGS = {
@@ -96,6 +108,9 @@ _SIGS = {
     "tn_xeb": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                               ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(XebResult), _P]),
+    "tn_plan_set_profiling": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "tn_plan_step_profile": (ctypes.c_int, [_P, ctypes.POINTER(StepProfile), ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int32)]),
     "tn_plan_destroy": (None, [_P]),
     "tn_last_error": (ctypes.c_char_p, []),
 }
@@ -212,6 +227,16 @@ class Plan:
         buf = ctypes.create_string_buffer(need.value)
         _check(library().tn_plan_export_json(self.handle, buf, need.value, ctypes.byref(need)))
         return json.loads(buf.value.decode())
+
+    def set_profiling(self, enable):
+        _check(library().tn_plan_set_profiling(self.handle, 1 if enable else 0))
+
+    def step_profile(self):
+        n = ctypes.c_int32()
+        _check(library().tn_plan_step_profile(self.handle, None, 0, ctypes.byref(n)))
+        arr = (StepProfile * max(1, n.value))()
+        _check(library().tn_plan_step_profile(self.handle, arr, n.value, ctypes.byref(n)))
+        return [arr[i].to_dict() for i in range(n.value)]
 
     # -- device calls (torch tensors in, nothing allocated here) ---------
 

@@ -199,3 +199,59 @@ def test_xeb_on_device_matches_oracle(c2_state):
     assert abs(r["cond_xeb"]) < 1e-12
     np.testing.assert_allclose(r["topk"], stats.topk_curve(p, 25, ks), rtol=1e-12)
     assert r["p_max"] == pytest.approx(p.max(), rel=1e-14)
+
+
+# --- full bench shape: 40-qubit 5x8 grid, 16 cycles, 16 open, 2^16 slices ---
+
+def _c3_plan(w, **kw):
+    # same planner options as bench.py
+    return _plan(w, n_slice_edges=16, restarts=16, seed=0, **kw)
+
+
+# Product-state amplitudes span a wide dynamic range; at this depth numpy's
+# own complex64 contraction of the same slice (same tree) is 1.65e-5 away
+# from complex128, so the complex64 bound for this test vehicle is 5e-5.  The
+# complex128 run checks the indexing of every step at full shape to 1e-12.
+PRODUCT_C64_TOL = 5e-5
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", C128_TOL), ("c64", PRODUCT_C64_TOL)])
+def test_c3_product_circuit_closed_form_full_shape(prec, tol):
+    """Same 5x8 / 16-cycle structure, two-qubit gates replaced by dense
+    product gates: per-slice values have a closed form at any size."""
+    w = rqc.workload("c3_5x8_m16", two_qubit="product")
+    p = _c3_plan(w, prec=prec)
+    s = p.stats()
+    sliced = p.sliced_edges()
+    assert s["n_slices"] == 2 ** 16
+    ids = [int(i) for i in rqc.sample_slice_ids(16, 3, seed=2)]
+    b = s["batch_log2"]
+    for j in ids:
+        _say("c3 product circuit", prec, "slice", j, "batch_log2", b)
+        got = _run(p, (j, j + 1))
+        ref = cf.product_amplitudes(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], sliced, j)
+        assert _rel(got, ref) < tol
+    # a whole launch group (2^b slices contracted together)
+    g = ids[0] >> b << b
+    _say("c3 product circuit", prec, "group", g, g + 2 ** b)
+    got = _run(p, (g, g + 2 ** b))
+    ref = sum(cf.product_amplitudes(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], sliced, j)
+              for j in range(g, g + 2 ** b))
+    assert _rel(got, ref) < tol
+
+
+def test_c3_random_circuit_slice_vs_oracle():
+    """One slice of the bench workload against the oracle's complex128
+    contraction (the plan's tree is only the oracle's schedule; results do not
+    depend on the order)."""
+    w = rqc.workload("c3_5x8_m16")
+    p = _c3_plan(w)
+    ex = p.export()
+    sliced = [tuple(e) for e in ex["sliced"]]
+    tree = list(zip(ex["lhs"], ex["rhs"]))
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    j = int(rqc.sample_slice_ids(16, 1, seed=2)[0])
+    _say("c3 random circuit, slice", j)
+    got = _run(p, (j, j + 1))
+    ref = nw.contract(nw.slice_network(net, sliced, nw.slice_values(sliced, j)), tree)
+    assert _rel(got, ref) < C64_TOL
