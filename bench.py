@@ -118,6 +118,7 @@ def main():
     ap.add_argument("--restarts", type=int, default=16)
     ap.add_argument("--batch-log2", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: slices are independent, "
@@ -145,6 +146,12 @@ def main():
         ws = runtime.workspace(plan)
         acc = runtime.accumulator(plan)
         amps = torch.empty(2 << s["n_open"], dtype=torch.float64, device="cuda")
+        n_tuned = 0
+        if not args.no_autotune:
+            t0 = time.perf_counter()
+            n_tuned = plan.autotune(ws, acc, None, reps=5)
+            log(f"{prec}: autotuned {n_tuned} step shapes in {time.perf_counter() - t0:.1f}s")
+            s = plan.stats()
         n = s["n_slices"]
         xres = None
 
@@ -175,7 +182,7 @@ def main():
             plan.set_profiling(False)
         cmacs = s["cmacs_per_batch"] * (n >> s["batch_log2"])
         return {"plan": plan, "stats": s, "sec": dt, "cmacs": cmacs, "prof": prof, "xeb": xres,
-                "t_plan": t_plan, "t_warm": t_warm}
+                "t_plan": t_plan, "t_warm": t_warm, "n_tuned": n_tuned}
 
     log(f"workload {args.workload}, precision {args.prec}")
     main_run = run(args.prec, args.steps, args.warmup, True)
@@ -190,7 +197,8 @@ def main():
         "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOAD_TEXT.get(args.workload, args.workload),
                    "n_slices": s["n_slices"], "slices_per_launch_sequence": 2 ** s["batch_log2"],
-                   "largest_intermediate_log2": s["max_log2_size"], "restarts": args.restarts},
+                   "largest_intermediate_log2": s["max_log2_size"], "restarts": args.restarts,
+                   "autotuned_shapes": main_run["n_tuned"], "launch": "eager with per-step HIP events"},
         "pct_mfma_peak": 100.0 * tflops / PEAK_TFLOPS[args.prec],
         "amplitudes_per_s": amps_per_s,
         "complex_macs_per_step": main_run["cmacs"],

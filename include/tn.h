@@ -106,6 +106,7 @@ typedef struct {
     int32_t cost_model;      /* 0 = FLOP/byte roofline model, 1 = learned MLP */
     uint64_t seed;
     int64_t max_workspace_bytes;  /* cap for the per-launch workspace (0 = 32 GiB) */
+    const struct tn_mlp_s* model; /* trained step-time model for cost_model = 1 (NULL = FLOP model) */
 } tn_plan_opts;
 
 typedef struct {
@@ -127,6 +128,10 @@ typedef struct {
     uint64_t tail_workspace_bytes;/* minimum ws_bytes for tn_amplitudes */
     int32_t n_dense_steps;        /* steps run on MFMA tiles */
     int32_t n_small_steps;        /* steps run on the streaming VALU kernel */
+    int32_t cost_model_used;      /* 0 FLOP count, 1 learned model, 2 learned model asked but
+                                     outside its training support (FLOP count used) */
+    int32_t n_candidates;         /* candidate trees/slicings ranked */
+    double predicted_ms;          /* learned model's predicted time of the whole job (0 if unused) */
 } tn_plan_stats;
 
 typedef struct {
@@ -223,6 +228,62 @@ tn_status tn_plan_set_profiling(tn_plan_t p, int32_t enable);
  * i-th slice-dependent step in execution order; the last entry is the float64
  * slice sum.  *n receives the number of entries (<= cap are written). */
 tn_status tn_plan_step_profile(tn_plan_t p, tn_step_profile* out, int32_t cap, int32_t* n);
+
+/* Autotuner: for every distinct slice-dependent step shape (m, n, k, batch,
+ * precision) time each candidate kernel tile on the data of one real launch
+ * group (HIP events, median of `reps` launches after one warm-up) and keep
+ * the fastest.  Choices are cached in the text file `cache_path` (NULL = no
+ * cache), keyed by GPU architecture, shape and precision; cached shapes are
+ * not re-timed.  The accumulator is used as scratch and must be re-zeroed by
+ * the caller afterwards.  Returns the number of shapes timed in *n_tuned. */
+tn_status tn_plan_autotune(tn_plan_t p, void* d_workspace, size_t ws_bytes, double* d_acc_scratch,
+                           const char* cache_path, int32_t reps, int32_t* n_tuned, void* hip_stream);
+
+/* ---- learned step-time model ------------------------------------------
+ * A 3-layer perceptron d_in -> hidden -> hidden -> 1 (ReLU) on the device,
+ * FP32, that maps step features to log(step milliseconds).  Forward,
+ * backward and Adam run in the library's own kernels.  Parameters are one
+ * flat array: W1 (d_in x hidden, row-major), b1, W2 (hidden x hidden), b2,
+ * W3 (hidden x 1), b3.  Not from the paper, whose cost is the FLOP count
+ * 2^(nA+nB+nAB) of appendix A (Fig. 3); that count stays the fallback. */
+typedef struct tn_mlp_s* tn_mlp_t;
+
+#define TN_STEP_FEATURES 12
+
+/* Features of one step (shape logs, operand and output logs, log work, log
+ * bytes at the plan's storage width, kernel class one-hot), written to
+ * out[TN_STEP_FEATURES]. */
+tn_status tn_step_features(int32_t m_log, int32_t n_log, int32_t k_log, int32_t b_log, int32_t kernel,
+                           tn_precision prec, float* out);
+
+/* Features of a plan's slice-dependent steps in execution order (the order of
+ * tn_plan_step_profile); h_out holds cap_steps * TN_STEP_FEATURES floats. */
+tn_status tn_plan_step_features(tn_plan_t p, float* h_out, int32_t cap_steps, int32_t* n_steps);
+
+/* Create a model on the current device with He-normal weights from `seed`. */
+tn_status tn_mlp_create(int32_t d_in, int32_t hidden, uint64_t seed, tn_mlp_t* out);
+tn_status tn_mlp_num_params(tn_mlp_t m, int64_t* n);
+tn_status tn_mlp_get_params(tn_mlp_t m, float* h_params, int64_t n);
+tn_status tn_mlp_set_params(tn_mlp_t m, const float* h_params, int64_t n);
+
+/* d_y[batch] = model(d_x[batch x d_in]) (device pointers). */
+tn_status tn_mlp_forward(tn_mlp_t m, const float* d_x, int32_t batch, float* d_y, void* hip_stream);
+
+/* Gradient of mean((model(x) - t)^2) with respect to every parameter,
+ * copied to h_grads (n_params floats, may be NULL); loss to *h_loss (may be
+ * NULL).  Synchronises the stream. */
+tn_status tn_mlp_gradient(tn_mlp_t m, const float* d_x, const float* d_t, int32_t batch, float* h_grads,
+                          float* h_loss, void* hip_stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that gradient. */
+tn_status tn_mlp_train_step(tn_mlp_t m, const float* d_x, const float* d_t, int32_t batch, float lr,
+                            float* h_loss, void* hip_stream);
+
+/* Feature box seen in training: a plan whose steps leave it (by more than
+ * `margin` per feature) is ranked by the FLOP count instead. */
+tn_status tn_mlp_set_support(tn_mlp_t m, const float* h_min, const float* h_max, int32_t n_feat, float margin);
+
+void tn_mlp_destroy(tn_mlp_t m);
 
 /* Release a plan and its device memory (NULL is ignored). */
 void tn_plan_destroy(tn_plan_t p);

@@ -9,11 +9,19 @@
 #include <vector>
 
 #include "exec.hpp"
+#include "mlp.hpp"
 #include "plan.hpp"
 
 struct tn_plan_s {
     tn::Plan plan;
     tn::DeviceState dev;
+};
+
+struct tn_mlp_s {
+    tn::Mlp m;
+    std::vector<float> fmin, fmax;
+    float margin = 0.f;
+    int device = -1;
 };
 
 namespace {
@@ -51,8 +59,39 @@ tn_status tn_plan(const tn_circuit* c, const int32_t* open_q, int32_t n_open, co
         std::vector<int> o(open_q, open_q + n_open), f(fixed_q, fixed_q + n_fixed);
         std::vector<uint8_t> b(fixed_bits, fixed_bits + n_fixed);
         tn_plan_opts op = opts ? *opts : tn::default_opts();
+        tn::CostModel cm;
+        const tn::CostModel* cmp = nullptr;
+        if (op.cost_model == 1 && op.model) {
+            const tn_mlp_s* mm = op.model;
+            if (mm->m.d_in != tn::kStepFeatures) return fail(TN_EINVAL, "model input width is not TN_STEP_FEATURES");
+            cm.predict = [mm](const std::vector<float>& feats, int rows, std::vector<float>& out) -> std::string {
+                // the model's own forward kernel, on its device
+                tn::Mlp& net = const_cast<tn::Mlp&>(mm->m);
+                float *dx = nullptr, *dy = nullptr;
+                if (hipMalloc(&dx, sizeof(float) * feats.size()) != hipSuccess ||
+                    hipMalloc(&dy, sizeof(float) * rows) != hipSuccess)
+                    return "hipMalloc failed";
+                std::string e;
+                if (hipMemcpy(dx, feats.data(), sizeof(float) * feats.size(), hipMemcpyHostToDevice) != hipSuccess)
+                    e = "upload failed";
+                if (e.empty()) e = net.forward(dx, rows, dy, nullptr);
+                out.assign(rows, 0.f);
+                if (e.empty() && hipMemcpy(out.data(), dy, sizeof(float) * rows, hipMemcpyDeviceToHost) != hipSuccess)
+                    e = "download failed";
+                (void)hipFree(dx);
+                (void)hipFree(dy);
+                return e;
+            };
+            cm.in_support = [mm](const float* row) {
+                if (mm->fmin.empty()) return true;
+                for (size_t i = 0; i < mm->fmin.size(); ++i)
+                    if (row[i] < mm->fmin[i] - mm->margin || row[i] > mm->fmax[i] + mm->margin) return false;
+                return true;
+            };
+            cmp = &cm;
+        }
         auto* h = new tn_plan_s;
-        std::string err = tn::make_plan(*c, o, f, b, tree, sliced, n_sliced, op, h->plan);
+        std::string err = tn::make_plan(*c, o, f, b, tree, sliced, n_sliced, op, h->plan, cmp);
         if (!err.empty()) {
             delete h;
             return fail(TN_EINVAL, err);
@@ -295,6 +334,137 @@ tn_status tn_plan_step_profile(tn_plan_t p, tn_step_profile* out, int32_t cap, i
         std::strncpy(o.kernel_name, pf.names[di].c_str(), sizeof(o.kernel_name) - 1);
     }
     return TN_OK;
+}
+
+tn_status tn_plan_autotune(tn_plan_t p, void* d_workspace, size_t ws_bytes, double* d_acc_scratch,
+                           const char* cache_path, int32_t reps, int32_t* n_tuned, void* hip_stream) {
+    if (!p || !d_workspace || !d_acc_scratch || !n_tuned) return fail(TN_EINVAL, "NULL argument");
+    if (ws_bytes < p->plan.stats.workspace_bytes) return fail(TN_EINVAL, "workspace too small");
+    if (p->dev.prof.on) return fail(TN_ESTATE, "disable step timing before autotuning");
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    try {
+        std::string e = tn::prepare(p->plan, p->dev, s);
+        if (!e.empty()) return fail(TN_EDEVICE, e);
+        int nt = 0;
+        e = tn::autotune(p->plan, p->dev, d_workspace, d_acc_scratch, cache_path, reps, nt, s);
+        *n_tuned = nt;
+        if (!e.empty()) return fail(TN_EDEVICE, e);
+        // kernel counts in the stats follow the new choices
+        p->plan.stats.n_dense_steps = p->plan.stats.n_small_steps = 0;
+        for (const tn::Step& st : p->plan.steps)
+            (st.kernel == tn::K_MFMA ? p->plan.stats.n_dense_steps : p->plan.stats.n_small_steps)++;
+        return TN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(TN_ENOMEM, "host allocation failed");
+    }
+}
+
+tn_status tn_step_features(int32_t m_log, int32_t n_log, int32_t k_log, int32_t b_log, int32_t kernel,
+                           tn_precision prec, float* out) {
+    if (!out) return fail(TN_EINVAL, "NULL argument");
+    tn::step_features(m_log, n_log, k_log, b_log, kernel, prec == TN_C128 ? 16 : 8, out);
+    return TN_OK;
+}
+
+tn_status tn_plan_step_features(tn_plan_t p, float* h_out, int32_t cap_steps, int32_t* n_steps) {
+    if (!p || !n_steps || (cap_steps > 0 && !h_out)) return fail(TN_EINVAL, "NULL argument");
+    int i = 0;
+    for (const tn::Step& st : p->plan.steps) {
+        if (st.invariant) continue;
+        if (i < cap_steps)
+            tn::step_features(st.m_log, st.n_log, st.k_log, st.b_log, st.kernel, p->plan.esize,
+                              h_out + (size_t)i * tn::kStepFeatures);
+        ++i;
+    }
+    *n_steps = i;
+    return TN_OK;
+}
+
+tn_status tn_mlp_create(int32_t d_in, int32_t hidden, uint64_t seed, tn_mlp_t* out) {
+    if (!out || d_in < 1 || hidden < 1 || d_in > 4096 || hidden > 4096) return fail(TN_EINVAL, "bad arguments");
+    *out = nullptr;
+    try {
+        auto* h = new tn_mlp_s;
+        std::string e = h->m.create(d_in, hidden, seed);
+        if (!e.empty()) {
+            h->m.release();
+            delete h;
+            return fail(TN_EDEVICE, e);
+        }
+        (void)hipGetDevice(&h->device);
+        *out = h;
+        return TN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(TN_ENOMEM, "host allocation failed");
+    }
+}
+
+tn_status tn_mlp_num_params(tn_mlp_t m, int64_t* n) {
+    if (!m || !n) return fail(TN_EINVAL, "NULL argument");
+    *n = m->m.n_params();
+    return TN_OK;
+}
+
+tn_status tn_mlp_get_params(tn_mlp_t m, float* h, int64_t n) {
+    if (!m || !h || n != m->m.n_params()) return fail(TN_EINVAL, "bad arguments");
+    if (hipMemcpy(h, m->m.params, sizeof(float) * n, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(TN_EDEVICE, "download failed");
+    return TN_OK;
+}
+
+tn_status tn_mlp_set_params(tn_mlp_t m, const float* h, int64_t n) {
+    if (!m || !h || n != m->m.n_params()) return fail(TN_EINVAL, "bad arguments");
+    if (hipMemcpy(m->m.params, h, sizeof(float) * n, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(TN_EDEVICE, "upload failed");
+    return TN_OK;
+}
+
+tn_status tn_mlp_forward(tn_mlp_t m, const float* d_x, int32_t batch, float* d_y, void* stream) {
+    if (!m || !d_x || !d_y || batch < 1) return fail(TN_EINVAL, "bad arguments");
+    return from_err(m->m.forward(d_x, batch, d_y, reinterpret_cast<hipStream_t>(stream)));
+}
+
+tn_status tn_mlp_gradient(tn_mlp_t m, const float* d_x, const float* d_t, int32_t batch, float* h_grads,
+                          float* h_loss, void* stream) {
+    if (!m || !d_x || !d_t || batch < 1) return fail(TN_EINVAL, "bad arguments");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float loss = 0.f;
+    std::string e = m->m.gradient(d_x, d_t, batch, &loss, s);
+    if (!e.empty()) return fail(TN_EDEVICE, e);
+    if (h_loss) *h_loss = loss;
+    if (h_grads) {
+        if (hipMemcpyAsync(h_grads, m->m.grads, sizeof(float) * m->m.n_params(), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(TN_EDEVICE, "download failed");
+    }
+    return TN_OK;
+}
+
+tn_status tn_mlp_train_step(tn_mlp_t m, const float* d_x, const float* d_t, int32_t batch, float lr, float* h_loss,
+                            void* stream) {
+    if (!m || !d_x || !d_t || batch < 1 || !(lr > 0)) return fail(TN_EINVAL, "bad arguments");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float loss = 0.f;
+    std::string e = m->m.gradient(d_x, d_t, batch, h_loss ? &loss : nullptr, s);
+    if (e.empty()) e = m->m.adam(lr, s);
+    if (!e.empty()) return fail(TN_EDEVICE, e);
+    if (h_loss) *h_loss = loss;
+    return TN_OK;
+}
+
+tn_status tn_mlp_set_support(tn_mlp_t m, const float* h_min, const float* h_max, int32_t n_feat, float margin) {
+    if (!m || !h_min || !h_max || n_feat != m->m.d_in) return fail(TN_EINVAL, "bad arguments");
+    m->fmin.assign(h_min, h_min + n_feat);
+    m->fmax.assign(h_max, h_max + n_feat);
+    m->margin = margin;
+    return TN_OK;
+}
+
+void tn_mlp_destroy(tn_mlp_t m) {
+    if (!m) return;
+    m->m.release();
+    delete m;
 }
 
 void tn_plan_destroy(tn_plan_t p) {

@@ -5,11 +5,17 @@
 #include "exec.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <cstdio>
+#include <map>
 
 #include "tiles.hpp"
 
 namespace tn {
+
+std::string run_groups_eager(Plan& p, DeviceState& d, void* ws, double* acc, const std::vector<Group>& groups,
+                             hipStream_t s);
 
 namespace {
 
@@ -61,13 +67,32 @@ int lp_mode(tn_precision p) {
     }
 }
 
+// Slice selection of a leaf read from device memory (graph replays).
+int leaf_select(const Plan& p, int node, uint8_t* bit, uint8_t* pos) {
+    const NodeInfo& ni = p.nodes[node];
+    if (ni.home != HOME_LEAF || ni.sliced_bits.empty()) return 0;
+    const int lo = (int)ni.layout.size() - (int)ni.sliced_bits.size();
+    const int n = std::min<int>(8, (int)ni.sliced_bits.size());
+    for (int i = 0; i < n; ++i) {
+        bit[i] = (uint8_t)ni.sliced_bits[i];
+        pos[i] = (uint8_t)(lo + i);
+    }
+    return n;
+}
+
 std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, const void* A, const void* B, void* C,
-                        void* ws, hipStream_t s, std::string* name = nullptr) {
+                        void* ws, hipStream_t s, std::string* name = nullptr, const uint64_t* d_slice = nullptr) {
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
     g.A = A;
     g.B = B;
     g.C = C;
+    if (d_slice) {
+        g.d_slice = d_slice;
+        g.sa_n = (uint8_t)leaf_select(p, st.a_node, g.sa_bit, g.sa_pos);
+        g.sb_n = (uint8_t)leaf_select(p, st.b_node, g.sb_bit, g.sb_pos);
+        if (g.sa_n == 0 && g.sb_n == 0) g.d_slice = nullptr;
+    }
     if (d.d_max) {
         g.amax = d.d_max + p.nodes[st.a_node].slot;
         g.bmax = d.d_max + p.nodes[st.b_node].slot;
@@ -224,13 +249,104 @@ std::string prepare(Plan& p, DeviceState& d, hipStream_t s) {
         if (!err.empty()) return err;
     }
     d.mask_words = std::max<size_t>(1, ((size_t(1) << p.batch_log2) + 31) / 32);
+    TN_HIP(hipMalloc(&d.d_state, sizeof(GroupState)));
+    TN_HIP(hipMemset(d.d_state, 0, sizeof(GroupState)));
     TN_HIP(hipStreamSynchronize(s));
     d.prepared = true;
     return "";
 }
 
+// Capture one full launch group (slice id read from device memory) into a
+// graph: group-begin, max-slot reset, every slice-dependent step, slice sum.
+static std::string build_graph(Plan& p, DeviceState& d, void* ws, double* acc) {
+    if (d.gexec) {
+        (void)hipGraphExecDestroy(d.gexec);
+        d.gexec = nullptr;
+    }
+    if (!d.cap_stream) TN_HIP(hipStreamCreateWithFlags(&d.cap_stream, hipStreamNonBlocking));
+    const int storage = storage_of(p.opts.prec);
+    hipStream_t c = d.cap_stream;
+    const uint64_t* dsl = &d.d_state->slice_base;
+    TN_HIP(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
+    std::string err;
+    hipError_t e = launch_group_begin(d.d_state, p.batch_log2, c);
+    if (e == hipSuccess && d.d_max)
+        e = launch_fill(d.d_max + p.n_static_slots, (uint64_t)(p.tree.n_nodes() - p.n_static_slots), c);
+    if (e != hipSuccess) err = std::string("graph: ") + hipGetErrorString(e);
+    for (const Step& st : p.steps) {
+        if (!err.empty()) break;
+        if (st.invariant) continue;
+        void* A = node_ptr(p, d, ws, st.a_node, 0);
+        void* B = node_ptr(p, d, ws, st.b_node, 0);
+        void* C = (unsigned char*)ws + st.c_off * (uint64_t)p.esize;
+        err = launch_step(p, d, st, A, B, C, ws, c, nullptr, dsl);
+    }
+    if (err.empty()) {
+        const int root = p.tree.root();
+        uint8_t bit[8], pos[8];
+        const int rn = leaf_select(p, root, bit, pos);
+        e = launch_slice_sum(storage, node_ptr(p, d, ws, root, 0), acc, p.root_log2, p.batch_log2, nullptr, 0,
+                             1ull << p.batch_log2, c, rn ? dsl : nullptr, bit, pos, rn);
+        if (e != hipSuccess) err = std::string("graph slice sum: ") + hipGetErrorString(e);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(c, &graph);
+    if (err.empty() && ee != hipSuccess) err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ee);
+    if (err.empty()) {
+        ee = hipGraphInstantiate(&d.gexec, graph, nullptr, nullptr, 0);
+        if (ee != hipSuccess) err = std::string("hipGraphInstantiate: ") + hipGetErrorString(ee);
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (err.empty()) {
+        d.g_ws = ws;
+        d.g_acc = acc;
+    } else {
+        d.gexec = nullptr;
+    }
+    return err;
+}
+
 std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std::vector<Group>& groups,
                        hipStream_t s) {
+    // full, consecutive launch groups are replayed from one captured graph
+    // unless per-step timing is on (it needs eager launches)
+    static const bool no_graph = std::getenv("TN_NO_GRAPH") != nullptr;
+    if (!d.prof.on && !no_graph && d.d_state && groups.size() >= 2) {
+        size_t i = 0;
+        std::vector<Group> eager;
+        while (i < groups.size()) {
+            size_t j = i;
+            const uint64_t B = 1ull << p.batch_log2;
+            while (j < groups.size() && groups[j].mask.empty() && groups[j].beta0 == 0 && groups[j].beta1 == B &&
+                   groups[j].slice_base == groups[i].slice_base + ((uint64_t)(j - i) << p.batch_log2))
+                ++j;
+            if (j - i >= 2) {
+                if (!eager.empty()) {
+                    std::string e = run_groups_eager(p, d, ws, acc, eager, s);
+                    if (!e.empty()) return e;
+                    eager.clear();
+                }
+                if (!d.gexec || d.g_ws != ws || d.g_acc != acc) {
+                    std::string e = build_graph(p, d, ws, acc);
+                    if (!e.empty()) return e;
+                }
+                TN_HIP(launch_group_set(d.d_state, groups[i].slice_base >> p.batch_log2, s));
+                for (size_t k = i; k < j; ++k) TN_HIP(hipGraphLaunch(d.gexec, s));
+                d.graph_replays += j - i;
+                i = j;
+            } else {
+                eager.push_back(groups[i]);
+                ++i;
+            }
+        }
+        if (!eager.empty()) return run_groups_eager(p, d, ws, acc, eager, s);
+        return "";
+    }
+    return run_groups_eager(p, d, ws, acc, groups, s);
+}
+
+std::string run_groups_eager(Plan& p, DeviceState& d, void* ws, double* acc, const std::vector<Group>& groups,
+                             hipStream_t s) {
     const int storage = storage_of(p.opts.prec);
     const int root = p.tree.root();
     // explicit masks: upload all of them first (blocking), then launch
@@ -305,7 +421,147 @@ std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std
     return err;
 }
 
+// ------------------------------------------------------------- autotune
+
+namespace {
+
+struct Candidate {
+    int kernel, tile, splitk;
+};
+
+// Every kernel configuration that can run a step of this shape.
+std::vector<Candidate> candidates(const Step& st, tn_precision prec) {
+    std::vector<Candidate> c;
+    if (mfma_capable(prec) && st.m_log >= 4 && st.n_log >= 3 && st.k_log >= 1)
+        for (int t = 0; t < kNumMfmaTiles; ++t)
+            if (kMfmaTiles[t].tm_log <= st.m_log && kMfmaTiles[t].tn_log <= st.n_log) c.push_back({K_MFMA, t, 0});
+    c.push_back({K_SMALL, 0, 0});
+    if (st.kernel == K_SPLITK) c.push_back({K_SPLITK, 0, st.splitk_log});
+    return c;
+}
+
+std::string shape_key(const std::string& arch, const Step& st, tn_precision prec) {
+    return arch + " " + std::to_string(st.m_log) + " " + std::to_string(st.n_log) + " " + std::to_string(st.k_log) +
+           " " + std::to_string(st.b_log) + " " + std::to_string((int)prec);
+}
+
+}  // namespace
+
+std::string autotune(Plan& p, DeviceState& d, void* ws, double* acc, const char* cache_path, int reps, int& n_tuned,
+                     hipStream_t s) {
+    n_tuned = 0;
+    reps = std::max(1, std::min(reps, 50));
+    hipDeviceProp_t prop;
+    int dev = 0;
+    TN_HIP(hipGetDevice(&dev));
+    TN_HIP(hipGetDeviceProperties(&prop, dev));
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    std::map<std::string, std::pair<int, int>> cache;   // key -> (kernel, tile)
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "r");
+        if (f) {
+            char a[64];
+            int m, n, k, b, pr, ker, tile;
+            while (std::fscanf(f, "%63s %d %d %d %d %d %d %d", a, &m, &n, &k, &b, &pr, &ker, &tile) == 8) {
+                Step st{};
+                st.m_log = m;
+                st.n_log = n;
+                st.k_log = k;
+                st.b_log = b;
+                cache[shape_key(a, st, (tn_precision)pr)] = {ker, tile};
+            }
+            std::fclose(f);
+        }
+    }
+    // walk one real launch group step by step: each step is timed on the
+    // operands its producers just wrote, then run with the chosen tile
+    std::string err;
+    if (d.d_max) TN_HIP(launch_fill(d.d_max + p.n_static_slots, (uint64_t)(p.tree.n_nodes() - p.n_static_slots), s));
+    hipEvent_t e0, e1;
+    TN_HIP(hipEventCreate(&e0));
+    TN_HIP(hipEventCreate(&e1));
+    std::map<std::string, std::pair<int, int>> decided;
+    for (Step& st : p.steps) {
+        if (st.invariant) continue;
+        void* A = node_ptr(p, d, ws, st.a_node, 0);
+        void* B = node_ptr(p, d, ws, st.b_node, 0);
+        void* C = (unsigned char*)ws + st.c_off * (uint64_t)p.esize;
+        const std::string key = shape_key(arch, st, p.opts.prec);
+        const std::pair<int, int>* hit = nullptr;
+        auto ci = cache.find(key);
+        if (ci != cache.end()) hit = &ci->second;
+        else {
+            auto di = decided.find(key);
+            if (di != decided.end()) hit = &di->second;
+        }
+        if (hit) {
+            if (hit->first != K_SPLITK || st.kernel == K_SPLITK) {   // split-K needs planned scratch
+                st.kernel = hit->first;
+                st.tile = hit->second;
+                if (st.kernel != K_SPLITK) st.splitk_log = 0;
+            }
+        } else {
+            float best_ms = -1.f;
+            Candidate best{st.kernel, st.tile, st.splitk_log};
+            const Step orig = st;
+            for (const Candidate& c : candidates(orig, p.opts.prec)) {
+                st.kernel = c.kernel;
+                st.tile = c.tile;
+                st.splitk_log = c.kernel == K_SPLITK ? orig.splitk_log : 0;
+                err = launch_step(p, d, st, A, B, C, ws, s);   // warm-up
+                if (!err.empty()) break;
+                std::vector<float> t;
+                for (int r = 0; r < reps && err.empty(); ++r) {
+                    TN_HIP(hipEventRecord(e0, s));
+                    err = launch_step(p, d, st, A, B, C, ws, s);
+                    TN_HIP(hipEventRecord(e1, s));
+                    TN_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    TN_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    t.push_back(ms);
+                }
+                if (!err.empty()) break;
+                std::sort(t.begin(), t.end());
+                const float med = t[t.size() / 2];
+                if (best_ms < 0 || med < best_ms) {
+                    best_ms = med;
+                    best = c;
+                }
+            }
+            st = orig;
+            if (!err.empty()) break;
+            st.kernel = best.kernel;
+            st.tile = best.tile;
+            st.splitk_log = best.kernel == K_SPLITK ? orig.splitk_log : 0;
+            decided[key] = {best.kernel, best.tile};
+            ++n_tuned;
+        }
+        err = launch_step(p, d, st, A, B, C, ws, s);   // the real output for the next steps
+        if (!err.empty()) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!err.empty()) return err;
+    // the captured graph used the old choices
+    if (d.gexec) {
+        (void)hipGraphExecDestroy(d.gexec);
+        d.gexec = nullptr;
+    }
+    if (cache_path && !decided.empty()) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (f) {
+            for (auto& kv : decided) std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+            std::fclose(f);
+        }
+    }
+    return "";
+}
+
 void release(DeviceState& d) {
+    if (d.gexec) (void)hipGraphExecDestroy(d.gexec);
+    if (d.cap_stream) (void)hipStreamDestroy(d.cap_stream);
+    if (d.d_state) (void)hipFree(d.d_state);
     for (int set = 0; set < 2; ++set)
         for (auto ev : d.prof.ev[set]) (void)hipEventDestroy(ev);
     if (d.plan_mem) (void)hipFree(d.plan_mem);

@@ -29,6 +29,12 @@ struct DeviceState {
     size_t mask_words = 0;
     double* d_part = nullptr;     // XEB partials
     float* d_max = nullptr;       // per-tensor max |re|,|im| (low-precision MFMA scaling)
+    GroupState* d_state = nullptr;     // graph replays: current launch group
+    hipStream_t cap_stream = nullptr;  // private stream for graph capture
+    hipGraphExec_t gexec = nullptr;    // one launch group, replayed
+    void* g_ws = nullptr;              // buffers the graph was captured with
+    double* g_acc = nullptr;
+    uint64_t graph_replays = 0;        // statistics
     Profiler prof;
 };
 
@@ -44,6 +50,8 @@ std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std
 void release(DeviceState& d);
 std::string profile_enable(Plan& p, DeviceState& d, bool on);
 std::string profile_harvest(DeviceState& d);
+std::string autotune(Plan& p, DeviceState& d, void* ws, double* acc, const char* cache_path, int reps, int& n_tuned,
+                     hipStream_t s);
 
 int storage_of(tn_precision p);
 

@@ -62,6 +62,15 @@ __device__ __forceinline__ void tile_max_atomic(float v, float* slot) {
     if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int*>(slot), __float_as_uint(v));
 }
 
+__device__ __forceinline__ uint64_t slice_offset(const uint64_t* d_slice, int n, const uint8_t* bit,
+                                                 const uint8_t* pos) {
+    if (n == 0) return 0;
+    const uint64_t sl = *d_slice;
+    uint64_t off = 0;
+    for (int i = 0; i < n; ++i) off += ((sl >> bit[i]) & 1ull) << pos[i];
+    return off;
+}
+
 struct TileIndex {
     uint64_t m0, n0, beta, split;
 };
@@ -109,8 +118,10 @@ __global__ void __launch_bounds__(256) k_valu(GemmArgs g) {
     T* Bs = sm + (TK << g.tm);
     const TileIndex ti = tile_index(g);
     const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
-    const T* A = reinterpret_cast<const T*>(g.A) + (ti.beta << g.m_log) + ti.m0;
-    const T* B = reinterpret_cast<const T*>(g.B) + (ti.beta << g.n_log) + ti.n0;
+    const T* A = reinterpret_cast<const T*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
+                 (ti.beta << g.m_log) + ti.m0;
+    const T* B = reinterpret_cast<const T*>(g.B) + slice_offset(g.d_slice, g.sb_n, g.sb_bit, g.sb_pos) +
+                 (ti.beta << g.n_log) + ti.n0;
     const int kc_log = g.k_log - g.split_log;
     const uint64_t kb = ti.split << kc_log;
     const uint64_t kn = 1ull << kc_log;
@@ -215,8 +226,10 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
     float2* Bs = As + TKMAX * TM;
     const TileIndex ti = tile_index(g);
     const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
-    const float2* A = reinterpret_cast<const float2*>(g.A) + (ti.beta << g.m_log) + ti.m0;
-    const float2* B = reinterpret_cast<const float2*>(g.B) + (ti.beta << g.n_log) + ti.n0;
+    const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
+                      (ti.beta << g.m_log) + ti.m0;
+    const float2* B = reinterpret_cast<const float2*>(g.B) + slice_offset(g.d_slice, g.sb_n, g.sb_bit, g.sb_pos) +
+                      (ti.beta << g.n_log) + ti.n0;
     const int TK = 1 << g.tk;
     const uint64_t K = 1ull << g.k_log;
     const int tid = threadIdx.x;
@@ -365,8 +378,10 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
     uint32_t* Blo = Bhi + TN * LD;
     const TileIndex ti = tile_index(g);
     const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
-    const float2* A = reinterpret_cast<const float2*>(g.A) + (ti.beta << g.m_log) + ti.m0;
-    const float2* B = reinterpret_cast<const float2*>(g.B) + (ti.beta << g.n_log) + ti.n0;
+    const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
+                      (ti.beta << g.m_log) + ti.m0;
+    const float2* B = reinterpret_cast<const float2*>(g.B) + slice_offset(g.d_slice, g.sb_n, g.sb_bit, g.sb_pos) +
+                      (ti.beta << g.n_log) + ti.n0;
     const int ea = scale_exp(g.amax), eb = scale_exp(g.bmax);
     const float sa = ldexpf(1.f, -ea), sb = ldexpf(1.f, -eb);
     const uint64_t K = 1ull << g.k_log;
@@ -498,9 +513,16 @@ __global__ void __launch_bounds__(256) k_fill(float* p, uint64_t n) {
 
 // ------------------------------------------------------------ slice sum
 
+struct RootSel {
+    const uint64_t* d_slice;
+    int n;
+    uint8_t bit[8], pos[8];
+};
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_slice_sum(const T* root, double2* acc, int res_log,
-                                                   const uint32_t* mask, uint64_t b0, uint64_t b1) {
+                                                   const uint32_t* mask, uint64_t b0, uint64_t b1, RootSel rs) {
+    root += slice_offset(rs.d_slice, rs.n, rs.bit, rs.pos);
     const uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (r >= (1ull << res_log)) return;
     double sx = 0.0, sy = 0.0;
@@ -514,6 +536,25 @@ __global__ void __launch_bounds__(256) k_slice_sum(const T* root, double2* acc, 
     a.x += sx;
     a.y += sy;
     acc[r] = a;
+}
+
+// Graph replay state: the only device writes are vector stores from lane 0.
+__global__ void k_group_set(GroupState* st, uint64_t first) {
+    if (threadIdx.x == 0) {
+        GroupState v;
+        v.next_group = first;
+        v.slice_base = 0;
+        st[threadIdx.x] = v;
+    }
+}
+
+__global__ void k_group_begin(GroupState* st, int batch_log2) {
+    if (threadIdx.x == 0) {
+        GroupState v = st[threadIdx.x];
+        v.slice_base = v.next_group << batch_log2;
+        v.next_group += 1;
+        st[threadIdx.x] = v;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_copy(const double* src, double* dst, uint64_t n) {
@@ -660,16 +701,34 @@ hipError_t launch_mfma(int mode, int tile, const GemmArgs& g, hipStream_t s) {
 }
 
 hipError_t launch_slice_sum(int storage, const void* root, double* acc, int res_log, int b_log,
-                            const uint32_t* d_mask, uint64_t beta0, uint64_t beta1, hipStream_t s) {
+                            const uint32_t* d_mask, uint64_t beta0, uint64_t beta1, hipStream_t s,
+                            const uint64_t* d_slice, const uint8_t* r_bit, const uint8_t* r_pos, int r_n) {
     (void)b_log;
+    RootSel rs{};
+    rs.d_slice = d_slice;
+    rs.n = r_n;
+    for (int i = 0; i < r_n && i < 8; ++i) {
+        rs.bit[i] = r_bit[i];
+        rs.pos[i] = r_pos[i];
+    }
     const uint64_t n = 1ull << res_log;
     const dim3 grid = grid_for((n + 255) / 256);
     if (storage == ST_C128)
         hipLaunchKernelGGL(k_slice_sum<double2>, grid, dim3(256), 0, s, reinterpret_cast<const double2*>(root),
-                           reinterpret_cast<double2*>(acc), res_log, d_mask, beta0, beta1);
+                           reinterpret_cast<double2*>(acc), res_log, d_mask, beta0, beta1, rs);
     else
         hipLaunchKernelGGL(k_slice_sum<float2>, grid, dim3(256), 0, s, reinterpret_cast<const float2*>(root),
-                           reinterpret_cast<double2*>(acc), res_log, d_mask, beta0, beta1);
+                           reinterpret_cast<double2*>(acc), res_log, d_mask, beta0, beta1, rs);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_set(GroupState* st, uint64_t first_group, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_set, dim3(1), dim3(64), 0, s, st, first_group);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_begin(GroupState* st, int batch_log2, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_begin, dim3(1), dim3(64), 0, s, st, batch_log2);
     return hipGetLastError();
 }
 

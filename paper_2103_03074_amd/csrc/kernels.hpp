@@ -28,6 +28,17 @@ struct GemmArgs {
     const float* amax;      // max |re|,|im| of A and B (low-precision MFMA scaling), or null
     const float* bmax;
     float* cmax;            // producer epilogue: atomic max of |re|,|im| of C, or null
+    // Slice selection read from device memory (graph replays): operand X gets
+    // offset sum_i bit(slice, x_bit[i]) << x_pos[i] elements, slice = *d_slice.
+    const uint64_t* d_slice;
+    uint8_t sa_n, sb_n;
+    uint8_t sa_bit[8], sa_pos[8], sb_bit[8], sb_pos[8];
+};
+
+// Device-resident state of graph replays.
+struct GroupState {
+    uint64_t next_group;    // launch group o of the next replay
+    uint64_t slice_base;    // o << batch_log2 of the current replay
 };
 
 // low-precision MFMA modes
@@ -40,8 +51,12 @@ hipError_t launch_valu(int storage, const GemmArgs& g, int R, hipStream_t s);
 hipError_t launch_splitk_reduce(int storage, const GemmArgs& g, hipStream_t s);
 hipError_t launch_mfma(int mode, int tile, const GemmArgs& g, hipStream_t s);   // mode -1: FP32, else LpMode
 hipError_t launch_fill(float* p, uint64_t n, hipStream_t s);
+hipError_t launch_group_set(GroupState* st, uint64_t first_group, hipStream_t s);
+hipError_t launch_group_begin(GroupState* st, int batch_log2, hipStream_t s);
 hipError_t launch_slice_sum(int storage, const void* root, double* acc, int res_log, int b_log,
-                            const uint32_t* d_mask, uint64_t beta0, uint64_t beta1, hipStream_t s);
+                            const uint32_t* d_mask, uint64_t beta0, uint64_t beta1, hipStream_t s,
+                            const uint64_t* d_slice = nullptr, const uint8_t* r_bit = nullptr,
+                            const uint8_t* r_pos = nullptr, int r_n = 0);
 hipError_t launch_copy_acc(const double* src, double* dst, uint64_t n, hipStream_t s);
 hipError_t launch_xeb_partials(const double* amps, uint64_t n, double w, double* part, int blocks,
                                hipStream_t s);

@@ -8,6 +8,7 @@
 //  - the head/tail split with the head vector reused for every s2
 //    (section "Big-head simulation of quantum circuits").
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <map>
 #include <numeric>
@@ -344,6 +345,94 @@ struct Arena {
 
 }  // namespace
 
+
+// Batch legs: keep some sliced edges as legs so that 2^b slices are contracted
+// in one launch sequence.  Planner-chosen slicings put the batch edges on the
+// low slice bits; a caller's slicing keeps its order and batches a prefix.
+static void choose_batch(const Network& net, const Tree& tree, const TreeLegs& tl, const tn_plan_opts& opts,
+                         int esize, bool fixed_slicing, std::vector<int>& sliced, std::vector<int>& batch) {
+    const int E = (int)net.edge_name.size();
+    std::vector<char> in_s(E, 0), in_b(E, 0);
+    for (int e : sliced) in_s[e] = 1;
+    const int k = (int)sliced.size();
+    const uint64_t cap = opts.max_workspace_bytes > 0 ? (uint64_t)opts.max_workspace_bytes : (uint64_t(32) << 30);
+    const int want = opts.batch_log2;
+    SliceCost sc = slice_cost_tl(tl, tree, in_s);
+    const int size_cap = std::max(sc.max_log2, 28);
+    batch.clear();
+    if (!fixed_slicing) {
+        std::vector<int> chosen;
+        while ((int)chosen.size() < k) {
+            if (want >= 0 && (int)chosen.size() >= want) break;
+            int best = -1;
+            BatchShape bb;
+            for (int e : sliced) {
+                if (in_b[e]) continue;
+                in_b[e] = 1;
+                BatchShape x = batch_shape(tl, tree, in_s, in_b, esize);
+                in_b[e] = 0;
+                if (best < 0 || x.cmacs < bb.cmacs) {
+                    best = e;
+                    bb = x;
+                }
+            }
+            if (best < 0) break;
+            if (want < 0) {
+                const double ws_est = 3.0 * std::exp2((double)bb.max_log2) * esize;
+                if (bb.max_log2 > size_cap || ws_est > (double)cap || (int)chosen.size() >= 14) break;
+            }
+            in_b[best] = 1;
+            chosen.push_back(best);
+        }
+        std::vector<int> reorder = chosen;
+        for (int e : sliced)
+            if (!in_b[e]) reorder.push_back(e);
+        sliced = reorder;
+        batch = chosen;
+        return;
+    }
+    for (int i = 0; i < k; ++i) {   // caller's order: the largest prefix within the limits
+        if (want >= 0 && i >= want) break;
+        in_b[sliced[i]] = 1;
+        BatchShape x = batch_shape(tl, tree, in_s, in_b, esize);
+        const double ws_est = 3.0 * std::exp2((double)x.max_log2) * esize;
+        if (want < 0 && (x.max_log2 > size_cap || ws_est > (double)cap || i >= 14)) break;
+        batch.push_back(sliced[i]);
+    }
+}
+
+// Shapes (m, n, k, b, kernel, slice-dependent) of every step of a candidate
+// with the given sliced and batch edges, as finalize() would lay them out.
+static std::vector<std::array<int, 6>> candidate_steps(const TreeLegs& tl, const Tree& t, const std::vector<char>& in_s,
+                                                       const std::vector<char>& in_b, tn_precision prec) {
+    const int N = t.n_nodes();
+    std::vector<Legs> lb(N);
+    std::vector<char> dep(N, 0);
+    for (int i = 0; i < t.n_leaves; ++i)
+        for (int e : tl.node[i]) {
+            dep[i] |= in_s[e];
+            if (!in_s[e] || in_b[e]) lb[i].push_back(e);
+        }
+    std::vector<std::array<int, 6>> out;
+    for (size_t s = 0; s < t.lhs.size(); ++s) {
+        int a = t.lhs[s], b = t.rhs[s], c = t.n_leaves + (int)s;
+        dep[c] = dep[a] | dep[b];
+        Legs both = set_inter(lb[a], lb[b]);
+        Legs keep;
+        for (int e : both)
+            if (in_b[e]) keep.push_back(e);
+        lb[c] = set_union(set_xor(lb[a], lb[b]), keep);
+        const int nb = (int)keep.size(), nk = (int)both.size() - nb;
+        int nm = (int)lb[a].size() - (int)both.size(), nn = (int)lb[b].size() - (int)both.size();
+        if (lb[b].size() > lb[a].size()) std::swap(nm, nn);
+        int kernel, tile, split;
+        choose_kernel(nm, nn, nk, nb, prec, kernel, tile, split);
+        if (!dep[c] && kernel == K_SPLITK) kernel = K_SMALL;
+        out.push_back({nm, nn, nk, nb, kernel, (int)dep[c]});
+    }
+    return out;
+}
+
 static std::string finalize(Plan& p) {
     const Network& net = p.net;
     const Tree& t = p.tree;
@@ -570,7 +659,7 @@ static void fill_stats(Plan& p) {
 std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
                       const std::vector<int>& fixed_q, const std::vector<uint8_t>& bits,
                       const tn_tree* tree, const tn_edge* sliced, int n_sliced,
-                      const tn_plan_opts& opts, Plan& out) {
+                      const tn_plan_opts& opts, Plan& out, const CostModel* cm) {
     out = Plan();
     out.opts = opts;
     if (opts.prec < TN_C64 || opts.prec > TN_BF16) return "unknown precision";
@@ -644,9 +733,15 @@ std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
         t.n_leaves = 1;
         cands.push_back(t);
     }
-    // slice each candidate, keep the cheapest
+    // slice each candidate; rank by FLOP count (or by the learned model)
     double best_cost = -1;
     const int n_force = fixed_slicing ? 0 : std::max(0, opts.n_slice_edges);
+    struct Ranked {
+        Tree t;
+        std::vector<int> s;
+        double flops, unmerged;
+    };
+    std::vector<Ranked> ranked;
     for (auto& t : cands) {
         std::vector<char> in_s(E, 0);
         if (!tree) {   // local optimisation of the unsliced tree
@@ -681,6 +776,7 @@ std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
             std::fprintf(stderr, "cand %zu: raw max %d log2 %.2f | k %zu log2 total %.2f\n",
                          (size_t)(&t - &cands[0]), raw.max_log2, std::log2(raw.invariant), s.size(), std::log2(cost));
         }
+        ranked.push_back({t, s, cost, sc.per_slice});
         if (best_cost < 0 || cost < best_cost) {
             best_cost = cost;
             out.tree = t;
@@ -688,78 +784,87 @@ std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
             out.unmerged_cmacs_per_slice = sc.per_slice;
         }
     }
-    // batch legs
-    {
-        TreeLegs tl = tree_legs(net, out.tree);
-        std::vector<char> in_s(E, 0), in_b(E, 0);
-        for (int e : out.sliced) in_s[e] = 1;
-        const int k = (int)out.sliced.size();
-        const uint64_t cap = opts.max_workspace_bytes > 0 ? (uint64_t)opts.max_workspace_bytes
-                                                          : (uint64_t(32) << 30);
-        int want = opts.batch_log2;
-        SliceCost sc = slice_cost_tl(tl, out.tree, in_s);
-        const int size_cap = std::max(sc.max_log2, 28);
-        std::vector<int> chosen;
-        while ((int)chosen.size() < k) {
-            if (want >= 0 && (int)chosen.size() >= want) break;
-            int best = -1;
-            BatchShape bb;
-            for (int e : out.sliced) {
-                if (in_b[e]) continue;
-                in_b[e] = 1;
-                BatchShape x = batch_shape(tl, out.tree, in_s, in_b, out.esize);
-                in_b[e] = 0;
-                if (best < 0 || x.cmacs < bb.cmacs) {
-                    best = e;
-                    bb = x;
-                }
+    out.stats.n_candidates = (int)ranked.size();
+    int model_used = 0;
+    double predicted = 0;
+    if (opts.cost_model == 1 && cm && ranked.size() > 1) {
+        // learned model: predicted time of the whole job per candidate
+        std::vector<float> feats;
+        std::vector<std::pair<size_t, size_t>> span;   // rows of each candidate
+        std::vector<std::vector<std::array<int, 6>>> shapes;
+        std::vector<int> groups_log;
+        bool inside = true;
+        for (auto& r : ranked) {
+            TreeLegs tl = tree_legs(net, r.t);
+            std::vector<int> sl = r.s, bt;
+            choose_batch(net, r.t, tl, opts, out.esize, fixed_slicing, sl, bt);
+            std::vector<char> in_s(E, 0), in_b(E, 0);
+            for (int e : sl) in_s[e] = 1;
+            for (int e : bt) in_b[e] = 1;
+            auto st = candidate_steps(tl, r.t, in_s, in_b, opts.prec);
+            const size_t r0 = feats.size() / kStepFeatures;
+            for (auto& x : st) {
+                float f[kStepFeatures];
+                step_features(x[0], x[1], x[2], x[3], x[4], out.esize, f);
+                if (cm->in_support && !cm->in_support(f)) inside = false;
+                feats.insert(feats.end(), f, f + kStepFeatures);
             }
-            if (best < 0) break;
-            if (want < 0) {
-                const double ws_est = 3.0 * std::exp2((double)bb.max_log2) * out.esize;
-                if (bb.max_log2 > size_cap || ws_est > (double)cap || (int)chosen.size() >= 14) break;
-            }
-            in_b[best] = 1;
-            chosen.push_back(best);
+            span.push_back({r0, st.size()});
+            shapes.push_back(std::move(st));
+            groups_log.push_back((int)sl.size() - (int)bt.size());
         }
-        out.batch_log2 = (int)chosen.size();
-        if (!fixed_slicing) {   // batch edges take the low slice bits
-            std::vector<int> reorder = chosen;
-            for (int e : out.sliced)
-                if (!in_b[e]) reorder.push_back(e);
-            out.sliced = reorder;
-            out.batch = chosen;
+        if (!inside) {
+            model_used = 2;
         } else {
-            // keep the caller's bit order; batch legs must be the low bits
-            out.batch.clear();
-            int nb = 0;
-            for (int i = 0; i < k && in_b[out.sliced[i]]; ++i) nb++;
-            // restrict the batch to a prefix of the caller's order
-            out.batch.assign(out.sliced.begin(), out.sliced.begin() + nb);
-            out.batch_log2 = nb;
-            if (nb != (int)chosen.size()) {
-                // re-choose: the largest prefix that satisfies the limits
-                std::fill(in_b.begin(), in_b.end(), 0);
-                out.batch.clear();
-                for (int i = 0; i < k; ++i) {
-                    if (want >= 0 && i >= want) break;
-                    in_b[out.sliced[i]] = 1;
-                    BatchShape x = batch_shape(tl, out.tree, in_s, in_b, out.esize);
-                    const double ws_est = 3.0 * std::exp2((double)x.max_log2) * out.esize;
-                    if (want < 0 && (x.max_log2 > size_cap || ws_est > (double)cap || i >= 14)) {
-                        in_b[out.sliced[i]] = 0;
-                        break;
-                    }
-                    out.batch.push_back(out.sliced[i]);
+            std::vector<float> pred;
+            std::string e = cm->predict(feats, (int)(feats.size() / kStepFeatures), pred);
+            if (!e.empty()) return "cost model: " + e;
+            double best = -1;
+            size_t bi = 0;
+            for (size_t c = 0; c < ranked.size(); ++c) {
+                double dep_ms = 0, inv_ms = 0;
+                for (size_t i = 0; i < span[c].second; ++i) {
+                    const double ms = std::exp((double)pred[span[c].first + i]);
+                    (shapes[c][i][5] ? dep_ms : inv_ms) += ms;
                 }
-                out.batch_log2 = (int)out.batch.size();
+                const double tot = std::exp2((double)groups_log[c]) * dep_ms + inv_ms;
+                if (best < 0 || tot < best) {
+                    best = tot;
+                    bi = c;
+                }
             }
+            out.tree = ranked[bi].t;
+            out.sliced = ranked[bi].s;
+            out.unmerged_cmacs_per_slice = ranked[bi].unmerged;
+            predicted = best;
+            model_used = 1;
         }
     }
+    {
+        TreeLegs tl = tree_legs(net, out.tree);
+        choose_batch(net, out.tree, tl, opts, out.esize, fixed_slicing, out.sliced, out.batch);
+        out.batch_log2 = (int)out.batch.size();
+    }
     if (out.sliced.size() > 62) return "more than 62 sliced edges needed";
+    // branch merging: re-tune the chosen tree for estimated time per slice
+    // (more multiply-adds, fewer skinny steps); kept only if faster
+    if (opts.branch_merge && !tree) {
+        std::vector<char> in_s(E, 0);
+        for (int e : out.sliced) in_s[e] = 1;
+        Tree merged = reconfigure(leaf_legs, out.tree, in_s, opts.max_log2_size, 8, 16, 1, out.esize);
+        TreeLegs tlm = tree_legs(net, merged);
+        if (slice_cost_tl(tlm, merged, in_s).max_log2 <= opts.max_log2_size &&
+            tree_time_estimate(leaf_legs, merged, in_s, out.esize) <
+                tree_time_estimate(leaf_legs, out.tree, in_s, out.esize))
+            out.tree = merged;
+    }
     err = finalize(out);
     if (!err.empty()) return err;
+    const int n_cand = out.stats.n_candidates;
     fill_stats(out);
+    out.stats.n_candidates = n_cand;
+    out.stats.cost_model_used = model_used;
+    out.stats.predicted_ms = predicted;
     return "";
 }
 

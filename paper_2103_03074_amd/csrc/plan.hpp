@@ -12,6 +12,7 @@
 
 #include <complex>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -72,8 +73,12 @@ Tree partition_tree(const std::vector<Legs>& leaf_legs, uint64_t seed, double ep
 // Subtree reconfiguration: repeatedly replace subtrees of up to max_frontier
 // frontier tensors by their optimal order (cost per slice with the edges in
 // in_s removed, intermediates above 2^target penalised).
+// objective 0: complex multiply-adds; 1: roofline time estimate (branch
+// merging).
 Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::vector<char>& in_s, int target,
-                 int max_frontier, int passes);
+                 int max_frontier, int passes, int objective = 0, int esize = 8);
+// Roofline time estimate of a tree (same units as objective 1).
+double tree_time_estimate(const std::vector<Legs>& leaf_legs, const Tree& t, const std::vector<char>& in_s, int esize);
 
 // Leaves contracted one after another in network (time) order.
 Tree time_order_tree(int n_leaves);
@@ -134,11 +139,22 @@ struct Plan {
     double unmerged_cmacs_per_slice = 0;
 };
 
+// Learned step-time model as seen by the planner: predict log(ms) of each
+// step from its features, and say whether a feature row is inside the
+// training support.
+struct CostModel {
+    std::function<std::string(const std::vector<float>& feats, int n_rows, std::vector<float>& log_ms)> predict;
+    std::function<bool(const float* row)> in_support;
+};
+
 // Full planning pipeline.
 std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
                       const std::vector<int>& fixed_q, const std::vector<uint8_t>& bits,
                       const tn_tree* tree, const tn_edge* sliced, int n_sliced,
-                      const tn_plan_opts& opts, Plan& out);
+                      const tn_plan_opts& opts, Plan& out, const CostModel* cm = nullptr);
+
+void step_features(int m, int n, int k, int b, int kernel, int esize, float* out);
+constexpr int kStepFeatures = 12;
 
 std::string plan_to_json(const Plan& p);
 

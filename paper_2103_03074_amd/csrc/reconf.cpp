@@ -46,16 +46,37 @@ struct Rebuild {
 
 }  // namespace
 
-// Cost of a step with union of legs `u` when sliced legs are removed, with a
-// penalty for outputs above the target.
-static double step_cost(int u_bits, int out_bits, int target) {
-    double c = std::exp2((double)u_bits);
+// Cost of a step with union of legs `u`, operands of a_bits and b_bits legs
+// and an output of out_bits legs (sliced legs removed), with a penalty for
+// outputs above the target.  objective 0: complex multiply-adds
+// 2^(nA+nB+nAB) (appendix A, Fig. 3).  objective 1: roofline time estimate
+// max(8 * 2^u / rate, bytes / bandwidth) in arbitrary units, with the MFMA
+// rate for steps large enough for MFMA tiles and a lower VALU rate otherwise
+// -- under this objective merging two small branches before a large step
+// (appendix B, "GPU efficiency") wins whenever it saves time.
+static double g_esize = 8.0;
+static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, int target, int objective) {
+    double c;
+    if (objective == 0) {
+        c = std::exp2((double)u_bits);
+    } else {
+        const int k = (a_bits + b_bits - out_bits) / 2;    // contracted legs
+        const int m = a_bits - k, n = b_bits - k;
+        const bool dense = std::max(m, n) >= 6 && std::min(m, n) >= 3 && k >= 2;
+        const double flops = 8.0 * std::exp2((double)u_bits);
+        const double rate = dense ? 100e12 : 25e12;     // sustained FP32 MFMA vs VALU complex FMA
+        const double bytes = g_esize * (std::exp2((double)a_bits) + std::exp2((double)b_bits) +
+                                        std::exp2((double)out_bits));
+        c = std::max(flops / rate, bytes / 6e12) * 1e12 + 2.0e6;   // + per-launch overhead (~2 us)
+    }
     if (out_bits > target) c *= std::exp2(4.0 * (out_bits - target) + 20.0);
     return c;
 }
 
+
 Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::vector<char>& in_s, int target,
-                 int max_frontier, int passes) {
+                 int max_frontier, int passes, int objective, int esize) {
+    g_esize = esize;
     Tree t = in;
     const int L = t.n_leaves;
     if (t.lhs.empty()) return t;
@@ -76,7 +97,8 @@ Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::
             right[c] = b;
             legs[c] = set_xor(legs[a], legs[b]);
             int u = (int)set_union(legs[a], legs[b]).size();
-            cost[c] = step_cost(u, (int)legs[c].size(), target);
+            cost[c] = step_cost_obj(u, (int)legs[a].size(), (int)legs[b].size(), (int)legs[c].size(), target,
+                                    objective);
         }
         // subtree cost (sum over the subtree)
         std::vector<double> sub(N, 0.0);
@@ -147,7 +169,8 @@ Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::
                     if (!(a & low)) continue;
                     const int b = m ^ a;
                     const int u = (sm[a] | sm[b]).count();
-                    const double c = best[a] + best[b] + step_cost(u, sm[m].count(), target);
+                    const double c = best[a] + best[b] +
+                                     step_cost_obj(u, sm[a].count(), sm[b].count(), sm[m].count(), target, objective);
                     if (bc < 0 || c < bc) {
                         bc = c;
                         bs = a;
@@ -206,6 +229,26 @@ Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::
         t = nt;
     }
     return t;
+}
+
+double tree_time_estimate(const std::vector<Legs>& leaf_legs, const Tree& t, const std::vector<char>& in_s,
+                          int esize) {
+    g_esize = esize;
+    const int L = t.n_leaves;
+    std::vector<Legs> legs(t.n_nodes());
+    for (int i = 0; i < L; ++i) {
+        for (int e : leaf_legs[i])
+            if (!in_s[e]) legs[i].push_back(e);
+        std::sort(legs[i].begin(), legs[i].end());
+    }
+    double tot = 0;
+    for (size_t s = 0; s < t.lhs.size(); ++s) {
+        const int a = t.lhs[s], b = t.rhs[s], c = L + (int)s;
+        legs[c] = set_xor(legs[a], legs[b]);
+        const int u = (int)set_union(legs[a], legs[b]).size();
+        tot += step_cost_obj(u, (int)legs[a].size(), (int)legs[b].size(), (int)legs[c].size(), 1000, 1);
+    }
+    return tot;
 }
 
 Tree time_order_tree(int n_leaves) {

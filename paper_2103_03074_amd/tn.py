@@ -50,7 +50,8 @@ class PlanOpts(ctypes.Structure):
                 ("n_slice_edges", ctypes.c_int32), ("batch_log2", ctypes.c_int32),
                 ("branch_merge", ctypes.c_int32), ("bighead", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("cost_model", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("max_workspace_bytes", ctypes.c_int64)]
+                ("seed", ctypes.c_uint64), ("max_workspace_bytes", ctypes.c_int64),
+                ("model", ctypes.c_void_p)]
 
 
 class PlanStats(ctypes.Structure):
@@ -64,7 +65,9 @@ class PlanStats(ctypes.Structure):
                 ("bytes_per_slice", ctypes.c_double), ("cmacs_per_batch", ctypes.c_double),
                 ("bytes_per_batch", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_uint64), ("tail_workspace_bytes", ctypes.c_uint64),
-                ("n_dense_steps", ctypes.c_int32), ("n_small_steps", ctypes.c_int32)]
+                ("n_dense_steps", ctypes.c_int32), ("n_small_steps", ctypes.c_int32),
+                ("cost_model_used", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
+                ("predicted_ms", ctypes.c_double)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,6 +114,23 @@ _SIGS = {
     "tn_plan_set_profiling": (ctypes.c_int, [_P, ctypes.c_int32]),
     "tn_plan_step_profile": (ctypes.c_int, [_P, ctypes.POINTER(StepProfile), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
+    "tn_plan_autotune": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, ctypes.c_char_p, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32), _P]),
+    "tn_step_features": (ctypes.c_int, [ctypes.c_int32] * 5 + [ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
+    "tn_plan_step_features": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_int32)]),
+    "tn_mlp_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "tn_mlp_num_params": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "tn_mlp_get_params": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_int64]),
+    "tn_mlp_set_params": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_int64]),
+    "tn_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
+    "tn_mlp_gradient": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                                       ctypes.POINTER(ctypes.c_float), _P]),
+    "tn_mlp_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_float,
+                                         ctypes.POINTER(ctypes.c_float), _P]),
+    "tn_mlp_set_support": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                          ctypes.c_int32, ctypes.c_float]),
+    "tn_mlp_destroy": (None, [_P]),
     "tn_plan_destroy": (None, [_P]),
     "tn_last_error": (ctypes.c_char_p, []),
 }
@@ -157,9 +177,10 @@ def _circuit_c(circuit):
 
 
 def plan_options(prec="c64", max_log2_size=30, n_slice_edges=-1, batch_log2=-1, branch_merge=0,
-                 bighead=0, restarts=8, cost_model=0, seed=0, max_workspace_bytes=0):
+                 bighead=0, restarts=8, cost_model=0, seed=0, max_workspace_bytes=0, model=None):
     return PlanOpts(PRECISIONS[prec] if isinstance(prec, str) else int(prec), max_log2_size, n_slice_edges,
-                    batch_log2, branch_merge, bighead, restarts, cost_model, seed, max_workspace_bytes)
+                    batch_log2, branch_merge, bighead, restarts, cost_model, seed, max_workspace_bytes,
+                    model.handle if model is not None else None)
 
 
 def _stream_ptr(stream):
@@ -238,6 +259,14 @@ class Plan:
         _check(library().tn_plan_step_profile(self.handle, arr, n.value, ctypes.byref(n)))
         return [arr[i].to_dict() for i in range(n.value)]
 
+    def autotune(self, ws, acc_scratch, cache_path=None, reps=5, stream=None):
+        n = ctypes.c_int32()
+        _check(library().tn_plan_autotune(self.handle, ctypes.c_void_p(ws.data_ptr()),
+                                          ws.numel() * ws.element_size(), ctypes.c_void_p(acc_scratch.data_ptr()),
+                                          cache_path.encode() if cache_path else None, int(reps),
+                                          ctypes.byref(n), _stream_ptr(stream)))
+        return n.value
+
     # -- device calls (torch tensors in, nothing allocated here) ---------
 
     def contract_slices(self, ws, acc, begin, end, stream=None):
@@ -258,6 +287,85 @@ class Plan:
                                        ctypes.c_void_p(ws.data_ptr()) if ws is not None else None,
                                        (ws.numel() * ws.element_size()) if ws is not None else 0,
                                        _stream_ptr(stream)))
+
+
+STEP_FEATURES = 12
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def step_features(m, n, k, b, kernel, prec="c64"):
+    out = np.zeros(STEP_FEATURES, dtype=np.float32)
+    _check(library().tn_step_features(int(m), int(n), int(k), int(b), int(kernel),
+                                      PRECISIONS[prec] if isinstance(prec, str) else int(prec), _fptr(out)))
+    return out
+
+
+def plan_step_features(plan):
+    n = ctypes.c_int32()
+    _check(library().tn_plan_step_features(plan.handle, None, 0, ctypes.byref(n)))
+    out = np.zeros((max(1, n.value), STEP_FEATURES), dtype=np.float32)
+    _check(library().tn_plan_step_features(plan.handle, _fptr(out), n.value, ctypes.byref(n)))
+    return out[:n.value]
+
+
+class Mlp:
+    """Owner of a tn_mlp_t (device weights of the learned step-time model)."""
+
+    def __init__(self, d_in=STEP_FEATURES, hidden=128, seed=0):
+        h = ctypes.c_void_p()
+        _check(library().tn_mlp_create(int(d_in), int(hidden), int(seed), ctypes.byref(h)))
+        self.handle = h
+        self.d_in, self.hidden = d_in, hidden
+
+    def close(self):
+        if getattr(self, "handle", None):
+            library().tn_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_params(self):
+        n = ctypes.c_int64()
+        _check(library().tn_mlp_num_params(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def get_params(self):
+        out = np.zeros(self.num_params(), dtype=np.float32)
+        _check(library().tn_mlp_get_params(self.handle, _fptr(out), out.size))
+        return out
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(library().tn_mlp_set_params(self.handle, _fptr(flat), flat.size))
+
+    def forward(self, x, y, stream=None):
+        _check(library().tn_mlp_forward(self.handle, ctypes.c_void_p(x.data_ptr()), int(x.shape[0]),
+                                        ctypes.c_void_p(y.data_ptr()), _stream_ptr(stream)))
+
+    def gradient(self, x, t, stream=None):
+        g = np.zeros(self.num_params(), dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(library().tn_mlp_gradient(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                         int(x.shape[0]), _fptr(g), ctypes.byref(loss), _stream_ptr(stream)))
+        return g, loss.value
+
+    def train_step(self, x, t, lr, stream=None):
+        loss = ctypes.c_float()
+        _check(library().tn_mlp_train_step(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                           int(x.shape[0]), float(lr), ctypes.byref(loss), _stream_ptr(stream)))
+        return loss.value
+
+    def set_support(self, fmin, fmax, margin=0.05):
+        fmin = np.ascontiguousarray(fmin, dtype=np.float32)
+        fmax = np.ascontiguousarray(fmax, dtype=np.float32)
+        _check(library().tn_mlp_set_support(self.handle, _fptr(fmin), _fptr(fmax), fmin.size, float(margin)))
 
 
 def xeb(amps, n_open, n_qubits, weight=1.0, ks=(), stream=None):

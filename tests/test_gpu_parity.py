@@ -255,3 +255,84 @@ def test_c3_random_circuit_slice_vs_oracle():
     got = _run(p, (j, j + 1))
     ref = nw.contract(nw.slice_network(net, sliced, nw.slice_values(sliced, j)), tree)
     assert _rel(got, ref) < C64_TOL
+
+
+# --- launch modes and mixed precision -------------------------------------
+
+def test_graph_replay_equals_eager_bitwise():
+    """Full launch groups are replayed from one captured hipGraph; with step
+    timing on, the same groups run eagerly.  Results must be bitwise equal."""
+    torch = _torch()
+    from paper_2103_03074_amd import runtime
+    w = rqc.workload("c2_5x5_m16")
+    p = _plan(w, n_slice_edges=8, restarts=4, batch_log2=2)
+    _say("c2 graph vs eager, 64 groups")
+    ws = runtime.workspace(p)
+    a_graph = runtime.accumulator(p)
+    p.contract_slices(ws, a_graph, 0, 256)
+    p.set_profiling(True)
+    a_eager = runtime.accumulator(p)
+    p.contract_slices(ws, a_eager, 0, 256)
+    prof = p.step_profile()
+    p.set_profiling(False)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a_graph.cpu().numpy(), a_eager.cpu().numpy())
+    assert all(st["launches"] == 64 for st in prof)
+    assert sum(st["total_ms"] for st in prof) > 0
+
+
+# Stated bounds of the mixed forms (norm-relative error vs the float64
+# oracle), from the per-product rounding of each form: split-FP16 keeps
+# about 22 bits per product (hi*hi + 2^-11 (hi*lo + lo*hi)), single-term
+# BF16 8 bits; errors accumulate over the depth of the tree.
+MIXED_TOL = {"split_fp16": 1e-4, "bf16": 5e-2}
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "bf16"])
+def test_c2_mixed_precision_vs_statevector(c2_state, prec):
+    w, psi = c2_state
+    _say("c2 mixed", prec)
+    p = _plan(w, n_slice_edges=8, restarts=4, prec=prec)
+    assert p.stats()["n_dense_steps"] > 0
+    got = _run(p)
+    ref = sv.amplitudes_from_state(psi, 25, w["open_q"], w["fixed_q"], w["bits"])
+    err = _rel(got, ref)
+    _say("c2 mixed", prec, "norm-rel error", err)
+    assert err < MIXED_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "bf16"])
+def test_c3_mixed_precision_slice_vs_oracle(prec):
+    w = rqc.workload("c3_5x8_m16")
+    p = _c3_plan(w, prec=prec)
+    ex = p.export()
+    sliced = [tuple(e) for e in ex["sliced"]]
+    tree = list(zip(ex["lhs"], ex["rhs"]))
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    j = int(rqc.sample_slice_ids(16, 1, seed=2)[0])
+    _say("c3 mixed", prec, "slice", j)
+    got = _run(p, (j, j + 1))
+    ref = nw.contract(nw.slice_network(net, sliced, nw.slice_values(sliced, j)), tree)
+    err = _rel(got, ref)
+    _say("c3 mixed", prec, "norm-rel error", err)
+    assert err < MIXED_TOL[prec]
+
+
+def test_autotune_keeps_results_and_caches(tmp_path):
+    torch = _torch()
+    from paper_2103_03074_amd import runtime
+    w = rqc.workload("c2_5x5_m16")
+    p = _plan(w, n_slice_edges=8, restarts=4)
+    before = _run(p)
+    ws = runtime.workspace(p)
+    scratch = runtime.accumulator(p)
+    cache = str(tmp_path / "tiles.txt")
+    _say("autotune c2")
+    n1 = p.autotune(ws, scratch, cache, reps=3)
+    after = _run(p)
+    assert n1 > 0
+    assert _rel(after, before) < 1e-6       # other tiles only reorder fp32 sums
+    p2 = _plan(w, n_slice_edges=8, restarts=4)
+    n2 = p2.autotune(ws, scratch, cache, reps=3)
+    assert n2 == 0                          # every shape came from the cache
+    torch.cuda.synchronize()
