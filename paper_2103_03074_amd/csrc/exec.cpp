@@ -96,7 +96,10 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
     if (d.d_max) {
         g.amax = d.d_max + p.nodes[st.a_node].slot;
         g.bmax = d.d_max + p.nodes[st.b_node].slot;
-        g.cmax = d.d_max + p.nodes[st.node].slot;
+        // the output's max is needed only when an MFMA step consumes it
+        const int parent = p.nodes[st.node].parent;
+        if (parent >= 0 && p.step_of_node[parent] >= 0 && p.steps[p.step_of_node[parent]].kernel == K_MFMA)
+            g.cmax = d.d_max + p.nodes[st.node].slot;
     }
     const int mode = lp_mode(p.opts.prec);
     g.m_log = st.m_log;
@@ -120,7 +123,10 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
         const int k = st.k_log - g.split_log;
         const int r_log = (m + n >= 10) ? 2 : (m + n >= 9 ? 1 : 0);
         const int tile_log = std::min(8 + r_log, m + n);
-        g.tm = std::min(m, tile_log);
+        // keep all of a small N in the tile (else A is re-read once per
+        // N-tile), give M the rest, then any remainder back to N
+        g.tn = std::min(n, std::min(4, tile_log));
+        g.tm = std::min(m, tile_log - g.tn);
         g.tn = std::min(n, tile_log - g.tm);
         R = 1 << std::max(0, g.tm + g.tn - 8);
         const int limit = (int)(32768 / esz);

@@ -55,11 +55,23 @@ __device__ __forceinline__ uint64_t deposit(uint64_t x, const uint8_t* pos, int 
 __device__ __forceinline__ float cabsmax(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
 __device__ __forceinline__ float cabsmax(double2 v) { return (float)fmax(fabs(v.x), fabs(v.y)); }
 
-// Largest |re|, |im| of a tile into *slot: one vector atomic per wave (the
-// bit pattern of a non-negative float orders like an unsigned integer).
+// Largest |re|, |im| of a tile into *slot (the bit pattern of a non-negative
+// float orders like an unsigned integer).  Reduced over the block first; the
+// single vector atomic is skipped when the slot already holds a larger value,
+// so a large grid does not serialise on one address.  All threads of the
+// block must call it.
 __device__ __forceinline__ void tile_max_atomic(float v, float* slot) {
+    __shared__ float wmax[16];
     for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int*>(slot), __float_as_uint(v));
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) wmax[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < nw; ++i) v = fmaxf(v, wmax[i]);
+        unsigned int* p = reinterpret_cast<unsigned int*>(slot);
+        const unsigned int u = __float_as_uint(v);
+        if (u > __atomic_load_n(p, __ATOMIC_RELAXED)) atomicMax(p, u);
+    }
 }
 
 __device__ __forceinline__ uint64_t slice_offset(const uint64_t* d_slice, int n, const uint8_t* bit,

@@ -506,8 +506,14 @@ static std::string finalize(Plan& p) {
         Legs bat, kk;
         for (int e : both) (in_b[e] ? bat : kk).push_back(e);
         Legs M = set_minus(la, lb), Nn = set_minus(lb, la);
+        // order by position in C, batch edges last: batch legs then sit on
+        // high address bits of every tensor, so the tiles (one batch index
+        // each) always cover the lowest bits of their operands and outputs
         auto by_c = [&](Legs v) {
-            std::sort(v.begin(), v.end(), [&](int x, int y) { return posc.at(x) < posc.at(y); });
+            std::sort(v.begin(), v.end(), [&](int x, int y) {
+                if (in_b[x] != in_b[y]) return in_b[x] < in_b[y];
+                return posc.at(x) < posc.at(y);
+            });
             return v;
         };
         M = by_c(M);
@@ -566,6 +572,8 @@ static std::string finalize(Plan& p) {
         }
     p.n_invariant_steps = 0;
     for (auto& st : p.steps) p.n_invariant_steps += st.invariant;
+    p.step_of_node.assign(N, -1);
+    for (size_t i = 0; i < p.steps.size(); ++i) p.step_of_node[p.steps[i].node] = (int)i;
     // memory: plan arena holds leaves and invariant tensors; the workspace
     // holds dependent intermediates with liveness reuse plus split-K scratch
     uint64_t plan_top = 0;

@@ -129,6 +129,7 @@ struct Plan {
     int batch_log2 = 0;
     std::vector<NodeInfo> nodes;
     std::vector<Step> steps;        // execution order: invariant steps first
+    std::vector<int> step_of_node;  // node -> index in steps (-1 for leaves)
     int n_invariant_steps = 0;
     int esize = 8;                  // bytes per complex element of the storage
     uint64_t ws_elems = 0;          // per-batch workspace (elements), incl. split-K scratch

@@ -1,0 +1,89 @@
+"""Precision study on the 53-qubit, 20-cycle workload.
+
+256 slice ids are sampled (seed 2) out of the 2^k slices of the plan for the
+54-site diagonal grid with 53 active qubits, 20 open and 33 fixed.  The same
+tree and slicing are contracted in complex128 (the float64 recontraction),
+complex64, split-FP16 and BF16.  For each form the study reports the
+norm-relative error of the summed partial amplitudes against complex128, the
+time per slice, and XEB of the partial sums with every probability scaled by
+2^k / 256 (partial sums over a sample are not amplitudes; the scaled
+estimator is computed the same way for every form, so the XEB differences
+measure precision only).
+
+    python -m paper_2103_03074_amd.study --out result.json
+"""
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def log(*a):
+    print("[study]", *a, file=sys.stderr, flush=True)
+
+
+def precision_study(n_samples=256, precs=("c128", "c64", "split_fp16", "bf16"), restarts=16):
+    import torch
+    import rqc
+    from . import tn, runtime
+    w = rqc.workload("c4_diag53_m20")
+    base = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], restarts=restarts, seed=0, branch_merge=1)
+    ex = base.export()
+    tree = list(zip(ex["lhs"], ex["rhs"]))
+    sliced = [tuple(e) for e in ex["sliced"]]
+    k = len(sliced)
+    ids = [int(i) for i in rqc.sample_slice_ids(k, n_samples, seed=2)]
+    weight = float(2.0 ** k / len(ids))
+    out = {"n_qubits": w["circuit"].n_qubits, "n_open": len(w["open_q"]), "n_sliced": k,
+           "n_samples": len(ids), "weight": weight, "forms": {}}
+    amps = {}
+    for prec in precs:
+        p = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], tree=tree, sliced=sliced, prec=prec)
+        s = p.stats()
+        ws = runtime.workspace(p)
+        acc = runtime.accumulator(p)
+        p.contract_slice_list(ws, acc, ids[:1])       # prepares the plan on the device
+        torch.cuda.synchronize()
+        acc.zero_()
+        t0 = time.perf_counter()
+        p.contract_slice_list(ws, acc, ids)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        a = torch.empty(2 << s["n_open"], dtype=torch.float64, device="cuda")
+        p.amplitudes(acc, a, ws)
+        x = tn.xeb(a, s["n_open"], w["circuit"].n_qubits, weight, ks=[1, 2 ** (s["n_open"] - 4)])
+        amps[prec] = a.cpu().numpy().view(np.complex128)
+        out["forms"][prec] = {"seconds_per_slice": dt / len(ids), "cmacs_per_slice": s["cmacs_per_slice"],
+                              "TFLOP/s": 8.0 * s["cmacs_per_slice"] * len(ids) / dt / 1e12,
+                              "F_unif_scaled": x["F_unif"], "F_self_scaled": x["F_self"],
+                              "topk_xeb": x["topk"]}
+        log(prec, out["forms"][prec])
+        p.close()
+    ref = amps.get("c128")
+    if ref is not None:
+        for prec in precs:
+            d = amps[prec] - ref
+            out["forms"][prec]["norm_rel_err_vs_c128"] = float(np.linalg.norm(d) / np.linalg.norm(ref))
+            out["forms"][prec]["F_unif_delta_vs_c128"] = (out["forms"][prec]["F_unif_scaled"] -
+                                                          out["forms"]["c128"]["F_unif_scaled"])
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--samples", type=int, default=256)
+    ap.add_argument("--out", default="")
+    args = ap.parse_args()
+    res = precision_study(args.samples)
+    text = json.dumps(res)
+    print(text, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text + "\n")
+
+
+if __name__ == "__main__":
+    main()
