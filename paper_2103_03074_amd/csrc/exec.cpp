@@ -117,6 +117,8 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
         g.tm = kMfmaTiles[st.tile].tm_log;
         g.tn = kMfmaTiles[st.tile].tn_log;
         g.tk = std::min(kMfmaTiles[st.tile].tk_max_log, st.k_log);
+    } else if (st.kernel == K_STREAM) {
+        g.tm = g.tn = g.tk = 0;
     } else {
         const int m = st.m_log, n = st.n_log;
         g.split_log = st.kernel == K_SPLITK ? st.splitk_log : 0;
@@ -134,6 +136,12 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
         while (tk < k && (2 << tk) * ((1 << g.tm) + (1 << g.tn)) <= limit) ++tk;
         g.tk = tk;
         if (g.split_log > 0) g.scratch = (unsigned char*)ws + st.scratch_off * (uint64_t)p.esize;
+    }
+    if (st.kernel == K_STREAM) {
+        if (name) *name = storage == ST_C128 ? "k_stream<double2,1>" : "k_stream<float2,2>";
+        hipError_t e = launch_stream(storage, g, s);
+        if (e != hipSuccess) return std::string("stream launch: ") + hipGetErrorString(e);
+        return "";
     }
     // epilogue decode: tile bits of C sorted by address position
     std::vector<std::pair<int, int>> ep;
@@ -442,6 +450,9 @@ std::vector<Candidate> candidates(const Step& st, tn_precision prec) {
         for (int t = 0; t < kNumMfmaTiles; ++t)
             if (kMfmaTiles[t].tm_log <= st.m_log && kMfmaTiles[t].tn_log <= st.n_log) c.push_back({K_MFMA, t, 0});
     c.push_back({K_SMALL, 0, 0});
+    if (st.k_log <= 4 && st.n_log <= 4 && st.k_log + st.n_log <= 6 && st.m_log >= (prec == TN_C128 ? 8 : 9) &&
+        st.b_log <= 16)
+        c.push_back({K_STREAM, 0, 0});
     if (st.kernel == K_SPLITK) c.push_back({K_SPLITK, 0, st.splitk_log});
     return c;
 }

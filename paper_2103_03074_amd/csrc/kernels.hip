@@ -21,6 +21,8 @@
 //  k_xeb_*       float64 block partials of sum P, sum P^2, max, min
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace tn {
 
 namespace {
@@ -219,6 +221,68 @@ __global__ void __launch_bounds__(256) k_splitk_red(GemmArgs g) {
     reinterpret_cast<T*>(g.C)[off] = s;
 }
 
+// ------------------------------------------------------------- streaming
+
+// Big-times-small steps: K and N at most 16 (K*N <= 64), M large.  Each
+// thread owns V = 2 consecutive m (complex64: one 16-byte load per k), issues
+// all K loads before any arithmetic, reads B through uniform (scalar-cached)
+// loads, and stores its N x V outputs straight to their bit-scattered C
+// addresses; lines written partially by one lane are completed by its
+// neighbours and merged in L2 before they reach HBM.
+constexpr int kStreamKN = 64;
+
+template <typename T, int V>
+__global__ void __launch_bounds__(256) k_stream(GemmArgs g) {
+    using VT = typename std::conditional<V == 2, float4, T>::type;   // V consecutive complex values
+    const int K = 1 << g.k_log, N = 1 << g.n_log;
+    const uint64_t beta = blockIdx.y;
+    const uint64_t m0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * V;
+    const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
+    const T* A = reinterpret_cast<const T*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
+                 (beta << g.m_log);
+    const T* B = reinterpret_cast<const T*>(g.B) + slice_offset(g.d_slice, g.sb_n, g.sb_bit, g.sb_pos) +
+                 (beta << g.n_log);
+    const bool live = m0 < (1ull << g.m_log);
+    T a[16][V];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k < K && live) {
+            const VT v = *reinterpret_cast<const VT*>(A + (uint64_t)k * sAk + m0);
+            if constexpr (V == 2) {
+                a[k][0] = T{v.x, v.y};
+                a[k][1] = T{v.z, v.w};
+            } else {
+                a[k][0] = v;
+            }
+        }
+    }
+    float mx = 0.f;
+    if (live) {
+        const uint64_t cm0 = deposit(m0, g.cpm, 0, g.m_log) + deposit(beta, g.cpb, 0, g.b_log);
+        const uint64_t cm1 = V == 2 ? cm0 + (1ull << g.cpm[0]) : 0;   // m0 is even: m0 + 1 sets bit 0
+        T* C = reinterpret_cast<T*>(g.C);
+        for (int n = 0; n < N; ++n) {
+            T acc[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] = czero<T>();
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k < K) {
+                    const T b = B[(uint64_t)k * sBk + n];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[v] = cfma(acc[v], a[k][v], b);
+                }
+            }
+            const uint64_t cn = deposit((uint64_t)n, g.cpn, 0, g.n_log);
+            C[cm0 + cn] = acc[0];
+            if constexpr (V == 2) C[cm1 + cn] = acc[1];
+#pragma unroll
+            for (int v = 0; v < V; ++v) mx = fmaxf(mx, cabsmax(acc[v]));
+        }
+    }
+    if (g.cmax) tile_max_atomic(mx, g.cmax);
+}
+
 // ------------------------------------------------------------------ MFMA
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -254,18 +318,48 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
     for (int i = 0; i < WM; ++i)
 #pragma unroll
         for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (uint64_t k0 = 0; k0 < K; k0 += TK) {
-        for (int e = tid; e < TK * (TM / 2); e += 256) {
-            const int kk = e / (TM / 2), mm = 2 * (e % (TM / 2));
-            const float4 v = *reinterpret_cast<const float4*>(A + (k0 + kk) * sAk + mm);
-            *reinterpret_cast<float4*>(As + kk * TM + mm) = v;
+    // each thread moves at most PA (PB) float4 of the A (B) chunk; the next
+    // chunk is loaded into registers while the current one is multiplied
+    constexpr int PA = (TKMAX * (TM / 2) + 255) / 256, PB = (TKMAX * (TN / 2) + 255) / 256;
+    float4 ra[PA], rb[PB];
+    auto load_chunk = [&](uint64_t k0) {
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            const int e = tid + 256 * i;
+            if (e < TK * (TM / 2)) {
+                const int kk = e / (TM / 2), mm = 2 * (e % (TM / 2));
+                ra[i] = *reinterpret_cast<const float4*>(A + (k0 + kk) * sAk + mm);
+            }
         }
-        for (int e = tid; e < TK * (TN / 2); e += 256) {
-            const int kk = e / (TN / 2), nn = 2 * (e % (TN / 2));
-            const float4 v = *reinterpret_cast<const float4*>(B + (k0 + kk) * sBk + nn);
-            *reinterpret_cast<float4*>(Bs + kk * TN + nn) = v;
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int e = tid + 256 * i;
+            if (e < TK * (TN / 2)) {
+                const int kk = e / (TN / 2), nn = 2 * (e % (TN / 2));
+                rb[i] = *reinterpret_cast<const float4*>(B + (k0 + kk) * sBk + nn);
+            }
+        }
+    };
+    load_chunk(0);
+    for (uint64_t k0 = 0; k0 < K; k0 += TK) {
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            const int e = tid + 256 * i;
+            if (e < TK * (TM / 2)) {
+                const int kk = e / (TM / 2), mm = 2 * (e % (TM / 2));
+                *reinterpret_cast<float4*>(As + kk * TM + mm) = ra[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int e = tid + 256 * i;
+            if (e < TK * (TN / 2)) {
+                const int kk = e / (TN / 2), nn = 2 * (e % (TN / 2));
+                *reinterpret_cast<float4*>(Bs + kk * TN + nn) = rb[i];
+            }
         }
         __syncthreads();
+        if (k0 + TK < K) load_chunk(k0 + TK);
         for (int kk = 0; kk < TK; kk += 2) {
             const int kc = kk + kc_off;
             float a[WM], b[WN];
@@ -377,17 +471,17 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
     constexpr int TNR = WAVES_N * WN * 16;
     constexpr int TN = TNR / 2;
     constexpr int TK = 16;                  // complex k per chunk = one MFMA k-step (32 real)
-    constexpr int LD = TK + 4;              // packed (re, im) words per LDS row, padded
     constexpr bool SPLIT = MODE == LP_SPLIT_FP16;
     constexpr int PLANES = SPLIT ? 2 : 1;
-    constexpr int AB_WORDS = PLANES * (TM + TN) * LD;
+    constexpr int AB_WORDS = PLANES * TK * (TM + TN);
     constexpr int RP = (TM * TNR <= kMfmaSmemFloats) ? TM : kMfmaSmemFloats / TNR;
     constexpr int SM_WORDS = AB_WORDS > kMfmaSmemFloats ? AB_WORDS : kMfmaSmemFloats;
     __shared__ __attribute__((aligned(16))) uint32_t smem[SM_WORDS];
+    // LDS planes stored [k][m] / [k][n]: one packed (re, im) word per element
     uint32_t* Ahi = smem;
-    uint32_t* Alo = Ahi + TM * LD;
-    uint32_t* Bhi = smem + PLANES * TM * LD;
-    uint32_t* Blo = Bhi + TN * LD;
+    uint32_t* Alo = Ahi + TK * TM;
+    uint32_t* Bhi = smem + PLANES * TK * TM;
+    uint32_t* Blo = Bhi + TK * TN;
     const TileIndex ti = tile_index(g);
     const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
     const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
@@ -413,48 +507,64 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
 #pragma unroll
             for (int j = 0; j < (SPLIT ? WN : 1); ++j) accx[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-    for (uint64_t k0 = 0; k0 < K; k0 += TK) {
-        for (int e = tid; e < TK * TM; e += 256) {
-            const int kk = e / TM, mm = e % TM;
-            uint32_t hi = 0, lo = 0;
-            if (kk < TKe) {
-                float2 v = A[(k0 + kk) * sAk + mm];
-                v.x *= sa;
-                v.y *= sa;
-                split_pack<MODE>(v, hi, lo);
-            }
-            Ahi[mm * LD + kk] = hi;
-            if constexpr (SPLIT) Alo[mm * LD + kk] = lo;
+    constexpr int PA = (TK * TM + 255) / 256, PB = (TK * TN + 255) / 256;
+    float2 ra[PA], rb[PB];
+    auto load_chunk = [&](uint64_t k0) {
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            const int e = tid + 256 * i, kk = e / TM, mm = e % TM;
+            ra[i] = (e < TK * TM && kk < TKe) ? A[(k0 + kk) * sAk + mm] : float2{0.f, 0.f};
         }
-        for (int e = tid; e < TK * TN; e += 256) {
-            const int kk = e / TN, nn = e % TN;
-            uint32_t hi = 0, lo = 0;
-            if (kk < TKe) {
-                float2 v = B[(k0 + kk) * sBk + nn];
-                v.x *= sb;
-                v.y *= sb;
-                split_pack<MODE>(v, hi, lo);
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int e = tid + 256 * i, kk = e / TN, nn = e % TN;
+            rb[i] = (e < TK * TN && kk < TKe) ? B[(k0 + kk) * sBk + nn] : float2{0.f, 0.f};
+        }
+    };
+    load_chunk(0);
+    for (uint64_t k0 = 0; k0 < K; k0 += TK) {
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            const int e = tid + 256 * i;
+            if (e < TK * TM) {
+                uint32_t hi, lo;
+                split_pack<MODE>(float2{ra[i].x * sa, ra[i].y * sa}, hi, lo);
+                Ahi[e] = hi;
+                if constexpr (SPLIT) Alo[e] = lo;
             }
-            Bhi[nn * LD + kk] = hi;
-            if constexpr (SPLIT) Blo[nn * LD + kk] = lo;
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int e = tid + 256 * i;
+            if (e < TK * TN) {
+                uint32_t hi, lo;
+                split_pack<MODE>(float2{rb[i].x * sb, rb[i].y * sb}, hi, lo);
+                Bhi[e] = hi;
+                if constexpr (SPLIT) Blo[e] = lo;
+            }
         }
         __syncthreads();
+        if (k0 + TK < K) load_chunk(k0 + TK);
         uint4 ah[WM], al[SPLIT ? WM : 1], bh[WN], bl[SPLIT ? WN : 1];
 #pragma unroll
         for (int bm = 0; bm < WM; ++bm) {
             const int row = (wm * WM + bm) * 16 + lr;
-            ah[bm] = *reinterpret_cast<const uint4*>(Ahi + row * LD + 4 * lg);
-            if constexpr (SPLIT) al[bm] = *reinterpret_cast<const uint4*>(Alo + row * LD + 4 * lg);
+            const uint32_t* p = Ahi + (4 * lg) * TM + row;
+            ah[bm] = uint4{p[0], p[TM], p[2 * TM], p[3 * TM]};
+            if constexpr (SPLIT) {
+                const uint32_t* q = Alo + (4 * lg) * TM + row;
+                al[bm] = uint4{q[0], q[TM], q[2 * TM], q[3 * TM]};
+            }
         }
 #pragma unroll
         for (int bn = 0; bn < WN; ++bn) {
             const int jr = (wn * WN + bn) * 16 + lr;
             const int odd = jr & 1;
-            uint4 v = *reinterpret_cast<const uint4*>(Bhi + (jr >> 1) * LD + 4 * lg);
-            bh[bn] = uint4{bexp(v.x, odd), bexp(v.y, odd), bexp(v.z, odd), bexp(v.w, odd)};
+            const uint32_t* p = Bhi + (4 * lg) * TN + (jr >> 1);
+            bh[bn] = uint4{bexp(p[0], odd), bexp(p[TN], odd), bexp(p[2 * TN], odd), bexp(p[3 * TN], odd)};
             if constexpr (SPLIT) {
-                uint4 u = *reinterpret_cast<const uint4*>(Blo + (jr >> 1) * LD + 4 * lg);
-                bl[bn] = uint4{bexp(u.x, odd), bexp(u.y, odd), bexp(u.z, odd), bexp(u.w, odd)};
+                const uint32_t* q = Blo + (4 * lg) * TN + (jr >> 1);
+                bl[bn] = uint4{bexp(q[0], odd), bexp(q[TN], odd), bexp(q[2 * TN], odd), bexp(q[3 * TN], odd)};
             }
         }
 #pragma unroll
@@ -667,6 +777,20 @@ hipError_t launch_valu(int storage, const GemmArgs& g, int R, hipStream_t s) {
         }
     }
 #undef TN_VALU
+    return hipGetLastError();
+}
+
+hipError_t launch_stream(int storage, const GemmArgs& g, hipStream_t s) {
+    if (g.k_log > 4 || g.n_log > 4 || g.k_log + g.n_log > 6) return hipErrorInvalidValue;
+    if (storage == ST_C128) {
+        const uint64_t blocks = std::max<uint64_t>(1, (1ull << g.m_log) / 256);
+        if (g.m_log < 8) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_stream<double2, 1>), dim3((unsigned)blocks, 1u << g.b_log), dim3(256), 0, s, g);
+    } else {
+        if (g.m_log < 9) return hipErrorInvalidValue;
+        const uint64_t blocks = (1ull << g.m_log) / 512;
+        hipLaunchKernelGGL((k_stream<float2, 2>), dim3((unsigned)blocks, 1u << g.b_log), dim3(256), 0, s, g);
+    }
     return hipGetLastError();
 }
 

@@ -637,7 +637,7 @@ static void fill_stats(Plan& p) {
             bytes += st.bytes;
         }
         if (st.kernel == K_MFMA) s.n_dense_steps++;
-        else s.n_small_steps++;
+        else s.n_small_steps++;   // streaming, VALU tile and split-K
     }
     for (int c = p.tree.n_leaves; c < p.tree.n_nodes(); ++c)
         mx = std::max(mx, (int)p.nodes[c].legs.size() - (p.nodes[c].dep ? 0 : 0));

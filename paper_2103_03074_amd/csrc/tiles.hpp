@@ -29,7 +29,7 @@ inline bool mfma_capable(tn_precision p) { return p != TN_C128; }
 // (all sizes log2).  Dense steps go to MFMA tiles; steps whose output is tiny
 // but whose contracted dimension is long are split along K; everything else
 // (the big-times-small steps that dominate bond-dimension-2 networks) runs on
-// the streaming VALU kernel.
+// the streaming kernel, or the generic VALU tile kernel.
 inline void choose_kernel(int m, int n, int k, int b, tn_precision prec, int& kernel, int& tile,
                           int& splitk_log) {
     kernel = 0;
@@ -50,6 +50,11 @@ inline void choose_kernel(int m, int n, int k, int b, tn_precision prec, int& ke
             tile = best;
             return;
         }
+    }
+    // big-times-small: streaming kernel (one pass over A, all K loads in flight)
+    if (k <= 4 && n <= 4 && k + n <= 6 && m >= (prec == TN_C128 ? 8 : 9) && b <= 16) {
+        kernel = 3;
+        return;
     }
     if (m + n + b <= 14 && k >= 12) {
         kernel = 2;
