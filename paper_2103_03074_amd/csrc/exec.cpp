@@ -450,7 +450,7 @@ std::vector<Candidate> candidates(const Step& st, tn_precision prec) {
         for (int t = 0; t < kNumMfmaTiles; ++t)
             if (kMfmaTiles[t].tm_log <= st.m_log && kMfmaTiles[t].tn_log <= st.n_log) c.push_back({K_MFMA, t, 0});
     c.push_back({K_SMALL, 0, 0});
-    if (st.k_log <= 4 && st.n_log <= 4 && st.k_log + st.n_log <= 6 && st.m_log >= (prec == TN_C128 ? 8 : 9) &&
+    if (st.k_log <= 4 && st.n_log <= 4 && st.m_log >= (prec == TN_C128 ? 8 : 9) &&
         st.b_log <= 16)
         c.push_back({K_STREAM, 0, 0});
     if (st.kernel == K_SPLITK) c.push_back({K_SPLITK, 0, st.splitk_log});

@@ -274,8 +274,16 @@ __global__ void __launch_bounds__(256) k_stream(GemmArgs g) {
                 }
             }
             const uint64_t cn = deposit((uint64_t)n, g.cpn, 0, g.n_log);
-            C[cm0 + cn] = acc[0];
-            if constexpr (V == 2) C[cm1 + cn] = acc[1];
+            if constexpr (V == 2) {
+                if (g.cpm[0] == 0) {   // the two m values are adjacent in C: one 16-byte store
+                    *reinterpret_cast<float4*>(C + cm0 + cn) = float4{acc[0].x, acc[0].y, acc[1].x, acc[1].y};
+                } else {
+                    C[cm0 + cn] = acc[0];
+                    C[cm1 + cn] = acc[1];
+                }
+            } else {
+                C[cm0 + cn] = acc[0];
+            }
 #pragma unroll
             for (int v = 0; v < V; ++v) mx = fmaxf(mx, cabsmax(acc[v]));
         }
@@ -287,27 +295,88 @@ __global__ void __launch_bounds__(256) k_stream(GemmArgs g) {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaSmemFloats = 8192;   // 32 KiB: A/B chunk tiles, then C staging
+constexpr int kMfmaSmemFloats = 8192;   // LDS budget of a staging pass (32 KiB)
 
+// Epilogue decode restricted to one staging pass: the tile rows are staged
+// RP = 2^rp_log at a time; element f of pass p takes its pass-selecting m bits
+// (logical m bits >= rp_log) from p and its remaining tile bits, in C-address
+// order, from f.  Returns the address offset; ml is relative to the pass.
+__device__ __forceinline__ uint64_t decode_pass(const GemmArgs& g, int rp_log, int p, int f, int& ml, int& nl) {
+    uint64_t off = 0;
+    ml = 0;
+    nl = 0;
+    int j = 0;
+    for (int i = 0; i < g.ep_n; ++i) {
+        const int s = g.ep_src[i];
+        int bit;
+        if (s < 32 && s >= rp_log) {
+            bit = (p >> (s - rp_log)) & 1;
+        } else {
+            bit = (f >> j) & 1;
+            ++j;
+            if (s < 32) ml |= bit << s;
+            else nl |= bit << (s - 32);
+        }
+        off |= (uint64_t)bit << g.ep_pos[i];
+    }
+    return off;
+}
+
+// Stage a register tile through LDS pass by pass and write it in C-address
+// order.  put(i, j, v) writes accumulator value v of tile row i, real column
+// j; the caller provides the register walk as a lambda.
+template <int TM, int TNR, int RP, typename Walk>
+__device__ __forceinline__ void store_tile(const GemmArgs& g, float* fs, float2* C, Walk walk) {
+    constexpr int TN = TNR / 2;
+    constexpr int rp_log = __builtin_ctz(RP);
+    const float2* Cs = reinterpret_cast<const float2*>(fs);
+    for (int p0 = 0; p0 < TM; p0 += RP) {
+        walk([&](int i, int j, float v) {
+            if (i >= p0 && i < p0 + RP) fs[(i - p0) * TNR + j] = v;
+        });
+        __syncthreads();
+        for (int f = threadIdx.x; f < RP * TN; f += 256) {
+            int ml, nl;
+            const uint64_t off = decode_pass(g, rp_log, p0 >> rp_log, f, ml, nl);
+            C[off] = Cs[ml * TN + nl];
+        }
+        __syncthreads();
+    }
+}
+
+template <int TM, int TNR, int AB>
+struct MfmaLds {
+    static constexpr int PASS = (TM * TNR <= kMfmaSmemFloats) ? TM * TNR : AB;   // floats of one staging pass
+    static constexpr int RP0 = PASS / TNR;
+    static constexpr int RP = RP0 >= TM ? TM : (1 << (31 - __builtin_clz(RP0)));  // rows per pass (power of 2)
+    static constexpr int FLOATS = AB > RP * TNR ? AB : RP * TNR;
+};
+
+// Complex GEMM on FP32 MFMA (v_mfma_f32_16x16x4f32), 4 real products per
+// complex product: A' = [Re A | Im A] interleaved is read as stored, B is
+// expanded to its 2x2 real block [[re, im], [-im, re]] while the fragment is
+// built.  K runs in chunks of 16 complex (8 MFMA k-steps, fully unrolled);
+// a shorter K is zero-filled.  The next chunk is loaded into registers while
+// the current one is multiplied.
 template <int WM, int WN, int WAVES_M, int WAVES_N>
 __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
     constexpr int TM = WAVES_M * WM * 16;   // complex rows
     constexpr int TNR = WAVES_N * WN * 16;  // real columns
     constexpr int TN = TNR / 2;             // complex columns
-    constexpr int TKMAX = (16 * (TM + TN) * 2 <= kMfmaSmemFloats) ? 16 : 8;
-    static_assert(TKMAX * (TM + TN) * 2 <= kMfmaSmemFloats, "tile too large");
-    constexpr int RP = (TM * TNR <= kMfmaSmemFloats) ? TM : kMfmaSmemFloats / TNR;  // rows per epilogue pass
-    __shared__ __attribute__((aligned(16))) float smem[kMfmaSmemFloats];
+    constexpr int TK = 16;
+    constexpr int AB = TK * (TM + TN) * 2;  // floats of the A and B chunk tiles
+    using L = MfmaLds<TM, TNR, AB>;
+    __shared__ __attribute__((aligned(16))) float smem[L::FLOATS];
     float2* As = reinterpret_cast<float2*>(smem);
-    float2* Bs = As + TKMAX * TM;
+    float2* Bs = As + TK * TM;
     const TileIndex ti = tile_index(g);
     const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
     const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
                       (ti.beta << g.m_log) + ti.m0;
     const float2* B = reinterpret_cast<const float2*>(g.B) + slice_offset(g.d_slice, g.sb_n, g.sb_bit, g.sb_pos) +
                       (ti.beta << g.n_log) + ti.n0;
-    const int TK = 1 << g.tk;
     const uint64_t K = 1ull << g.k_log;
+    const int TKe = K < (uint64_t)TK ? (int)K : TK;
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63;
     const int wm = w % WAVES_M, wn = w / WAVES_M;
@@ -318,26 +387,20 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
     for (int i = 0; i < WM; ++i)
 #pragma unroll
         for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // each thread moves at most PA (PB) float4 of the A (B) chunk; the next
-    // chunk is loaded into registers while the current one is multiplied
-    constexpr int PA = (TKMAX * (TM / 2) + 255) / 256, PB = (TKMAX * (TN / 2) + 255) / 256;
+    constexpr int PA = (TK * (TM / 2) + 255) / 256, PB = (TK * (TN / 2) + 255) / 256;
     float4 ra[PA], rb[PB];
     auto load_chunk = [&](uint64_t k0) {
 #pragma unroll
         for (int i = 0; i < PA; ++i) {
-            const int e = tid + 256 * i;
-            if (e < TK * (TM / 2)) {
-                const int kk = e / (TM / 2), mm = 2 * (e % (TM / 2));
-                ra[i] = *reinterpret_cast<const float4*>(A + (k0 + kk) * sAk + mm);
-            }
+            const int e = tid + 256 * i, kk = e / (TM / 2), mm = 2 * (e % (TM / 2));
+            ra[i] = (e < TK * (TM / 2) && kk < TKe) ? *reinterpret_cast<const float4*>(A + (k0 + kk) * sAk + mm)
+                                                   : float4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
         for (int i = 0; i < PB; ++i) {
-            const int e = tid + 256 * i;
-            if (e < TK * (TN / 2)) {
-                const int kk = e / (TN / 2), nn = 2 * (e % (TN / 2));
-                rb[i] = *reinterpret_cast<const float4*>(B + (k0 + kk) * sBk + nn);
-            }
+            const int e = tid + 256 * i, kk = e / (TN / 2), nn = 2 * (e % (TN / 2));
+            rb[i] = (e < TK * (TN / 2) && kk < TKe) ? *reinterpret_cast<const float4*>(B + (k0 + kk) * sBk + nn)
+                                                   : float4{0.f, 0.f, 0.f, 0.f};
         }
     };
     load_chunk(0);
@@ -345,21 +408,16 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < PA; ++i) {
             const int e = tid + 256 * i;
-            if (e < TK * (TM / 2)) {
-                const int kk = e / (TM / 2), mm = 2 * (e % (TM / 2));
-                *reinterpret_cast<float4*>(As + kk * TM + mm) = ra[i];
-            }
+            if (e < TK * (TM / 2)) *reinterpret_cast<float4*>(As + 2 * e) = ra[i];
         }
 #pragma unroll
         for (int i = 0; i < PB; ++i) {
             const int e = tid + 256 * i;
-            if (e < TK * (TN / 2)) {
-                const int kk = e / (TN / 2), nn = 2 * (e % (TN / 2));
-                *reinterpret_cast<float4*>(Bs + kk * TN + nn) = rb[i];
-            }
+            if (e < TK * (TN / 2)) *reinterpret_cast<float4*>(Bs + 2 * e) = rb[i];
         }
         __syncthreads();
         if (k0 + TK < K) load_chunk(k0 + TK);
+#pragma unroll
         for (int kk = 0; kk < TK; kk += 2) {
             const int kc = kk + kc_off;
             float a[WM], b[WN];
@@ -372,7 +430,6 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
             for (int bn = 0; bn < WN; ++bn) {
                 const int jr = (wn * WN + bn) * 16 + lr;
                 const float2 v = Bs[kc * TN + (jr >> 1)];
-                // real expansion of B: rows (k, re|im), columns (n, re|im)
                 b[bn] = (jr & 1) == 0 ? (comp == 0 ? v.x : -v.y) : (comp == 0 ? v.y : v.x);
             }
 #pragma unroll
@@ -383,11 +440,6 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
         }
         __syncthreads();
     }
-    // epilogue: stage RP rows at a time, write in C-address order
-    const uint64_t cbase = deposit(ti.m0, g.cpm, g.tm, g.m_log) + deposit(ti.n0, g.cpn, g.tn, g.n_log) +
-                           deposit(ti.beta, g.cpb, 0, g.b_log);
-    float2* C = reinterpret_cast<float2*>(g.C) + cbase;
-    const float2* Cs = reinterpret_cast<const float2*>(smem);
     if (g.cmax) {
         float mx = 0.f;
 #pragma unroll
@@ -398,27 +450,17 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
                 for (int r = 0; r < 4; ++r) mx = fmaxf(mx, fabsf(acc[bm][bn][r]));
         tile_max_atomic(mx, g.cmax);
     }
-    for (int p0 = 0; p0 < TM; p0 += RP) {
+    const uint64_t cbase = deposit(ti.m0, g.cpm, g.tm, g.m_log) + deposit(ti.n0, g.cpn, g.tn, g.n_log) +
+                           deposit(ti.beta, g.cpb, 0, g.b_log);
+    store_tile<TM, TNR, L::RP>(g, smem, reinterpret_cast<float2*>(g.C) + cbase, [&](auto put) {
 #pragma unroll
         for (int bm = 0; bm < WM; ++bm)
 #pragma unroll
             for (int bn = 0; bn < WN; ++bn)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = (wm * WM + bm) * 16 + 4 * lq + r;
-                    if (i >= p0 && i < p0 + RP) {
-                        const int jr = (wn * WN + bn) * 16 + lr;
-                        smem[(i - p0) * TNR + jr] = acc[bm][bn][r];
-                    }
-                }
-        __syncthreads();
-        for (int x = tid; x < TM * TN; x += 256) {
-            int ml, nl;
-            const uint64_t off = decode_ep(g, x, ml, nl);
-            if (ml >= p0 && ml < p0 + RP) C[off] = Cs[(ml - p0) * TN + nl];
-        }
-        __syncthreads();
-    }
+                for (int r = 0; r < 4; ++r)
+                    put((wm * WM + bm) * 16 + 4 * lq + r, (wn * WN + bn) * 16 + lr, acc[bm][bn][r]);
+    });
 }
 
 // ------------------------------------------------- low-precision MFMA
@@ -426,21 +468,25 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// pack two reals (re in the low half) after scaling
+typedef __fp16 half2v __attribute__((ext_vector_type(2)));
+
+// Pack two reals (re in the low half) after scaling by s.  FP16 uses the
+// packed round-toward-zero conversion; in split mode the remainder
+// x - hi is exact in FP32, so the rounding of hi is carried by lo
+// (stored scaled by 2^11 so it stays normal in FP16).
 template <int MODE>
-__device__ __forceinline__ void split_pack(float2 v, uint32_t& hi, uint32_t& lo) {
+__device__ __forceinline__ void split_pack(float2 v, float s, uint32_t& hi, uint32_t& lo) {
     if constexpr (MODE == LP_BF16) {
-        const __bf16 r = (__bf16)v.x, i = (__bf16)v.y;
+        const __bf16 r = (__bf16)(v.x * s), i = (__bf16)(v.y * s);
         hi = (uint32_t)__builtin_bit_cast(uint16_t, r) | ((uint32_t)__builtin_bit_cast(uint16_t, i) << 16);
         lo = 0;
     } else {
-        const _Float16 r = (_Float16)v.x, i = (_Float16)v.y;
-        hi = (uint32_t)__builtin_bit_cast(uint16_t, r) | ((uint32_t)__builtin_bit_cast(uint16_t, i) << 16);
+        const float xr = v.x * s, xi = v.y * s;
+        const half2v h = __builtin_amdgcn_cvt_pkrtz(xr, xi);
+        hi = __builtin_bit_cast(uint32_t, h);
         if constexpr (MODE == LP_SPLIT_FP16) {
-            // remainder scaled by 2^11 so it stays normal in FP16
-            const _Float16 lr = (_Float16)((v.x - (float)r) * 2048.f);
-            const _Float16 li = (_Float16)((v.y - (float)i) * 2048.f);
-            lo = (uint32_t)__builtin_bit_cast(uint16_t, lr) | ((uint32_t)__builtin_bit_cast(uint16_t, li) << 16);
+            const half2v l = __builtin_amdgcn_cvt_pkrtz((xr - (float)h.x) * 2048.f, (xi - (float)h.y) * 2048.f);
+            lo = __builtin_bit_cast(uint32_t, l);
         } else {
             lo = 0;
         }
@@ -470,13 +516,12 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
     constexpr int TM = WAVES_M * WM * 16;
     constexpr int TNR = WAVES_N * WN * 16;
     constexpr int TN = TNR / 2;
-    constexpr int TK = 16;                  // complex k per chunk = one MFMA k-step (32 real)
+    constexpr int TK = 32;                  // complex k per chunk = two MFMA k-steps (32 real each)
     constexpr bool SPLIT = MODE == LP_SPLIT_FP16;
     constexpr int PLANES = SPLIT ? 2 : 1;
     constexpr int AB_WORDS = PLANES * TK * (TM + TN);
-    constexpr int RP = (TM * TNR <= kMfmaSmemFloats) ? TM : kMfmaSmemFloats / TNR;
-    constexpr int SM_WORDS = AB_WORDS > kMfmaSmemFloats ? AB_WORDS : kMfmaSmemFloats;
-    __shared__ __attribute__((aligned(16))) uint32_t smem[SM_WORDS];
+    using L = MfmaLds<TM, TNR, AB_WORDS>;
+    __shared__ __attribute__((aligned(16))) uint32_t smem[L::FLOATS];
     // LDS planes stored [k][m] / [k][n]: one packed (re, im) word per element
     uint32_t* Ahi = smem;
     uint32_t* Alo = Ahi + TK * TM;
@@ -528,7 +573,7 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
             const int e = tid + 256 * i;
             if (e < TK * TM) {
                 uint32_t hi, lo;
-                split_pack<MODE>(float2{ra[i].x * sa, ra[i].y * sa}, hi, lo);
+                split_pack<MODE>(ra[i], sa, hi, lo);
                 Ahi[e] = hi;
                 if constexpr (SPLIT) Alo[e] = lo;
             }
@@ -538,21 +583,23 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
             const int e = tid + 256 * i;
             if (e < TK * TN) {
                 uint32_t hi, lo;
-                split_pack<MODE>(float2{rb[i].x * sb, rb[i].y * sb}, hi, lo);
+                split_pack<MODE>(rb[i], sb, hi, lo);
                 Bhi[e] = hi;
                 if constexpr (SPLIT) Blo[e] = lo;
             }
         }
         __syncthreads();
         if (k0 + TK < K) load_chunk(k0 + TK);
+#pragma unroll
+        for (int ks = 0; ks < TK; ks += 16) {
         uint4 ah[WM], al[SPLIT ? WM : 1], bh[WN], bl[SPLIT ? WN : 1];
 #pragma unroll
         for (int bm = 0; bm < WM; ++bm) {
             const int row = (wm * WM + bm) * 16 + lr;
-            const uint32_t* p = Ahi + (4 * lg) * TM + row;
+            const uint32_t* p = Ahi + (ks + 4 * lg) * TM + row;
             ah[bm] = uint4{p[0], p[TM], p[2 * TM], p[3 * TM]};
             if constexpr (SPLIT) {
-                const uint32_t* q = Alo + (4 * lg) * TM + row;
+                const uint32_t* q = Alo + (ks + 4 * lg) * TM + row;
                 al[bm] = uint4{q[0], q[TM], q[2 * TM], q[3 * TM]};
             }
         }
@@ -560,10 +607,10 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
         for (int bn = 0; bn < WN; ++bn) {
             const int jr = (wn * WN + bn) * 16 + lr;
             const int odd = jr & 1;
-            const uint32_t* p = Bhi + (4 * lg) * TN + (jr >> 1);
+            const uint32_t* p = Bhi + (ks + 4 * lg) * TN + (jr >> 1);
             bh[bn] = uint4{bexp(p[0], odd), bexp(p[TN], odd), bexp(p[2 * TN], odd), bexp(p[3 * TN], odd)};
             if constexpr (SPLIT) {
-                const uint32_t* q = Blo + (4 * lg) * TN + (jr >> 1);
+                const uint32_t* q = Blo + (ks + 4 * lg) * TN + (jr >> 1);
                 bl[bn] = uint4{bexp(q[0], odd), bexp(q[TN], odd), bexp(q[2 * TN], odd), bexp(q[3 * TN], odd)};
             }
         }
@@ -585,6 +632,7 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
                     }
                 }
             }
+        }
         __syncthreads();
     }
     // undo the scaling exactly and fold in the cross terms
@@ -605,27 +653,16 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
     if (g.cmax) tile_max_atomic(mx, g.cmax);
     const uint64_t cbase = deposit(ti.m0, g.cpm, g.tm, g.m_log) + deposit(ti.n0, g.cpn, g.tn, g.n_log) +
                            deposit(ti.beta, g.cpb, 0, g.b_log);
-    float2* C = reinterpret_cast<float2*>(g.C) + cbase;
-    float* fs = reinterpret_cast<float*>(smem);
-    const float2* Cs = reinterpret_cast<const float2*>(smem);
-    for (int p0 = 0; p0 < TM; p0 += RP) {
+    store_tile<TM, TNR, L::RP>(g, reinterpret_cast<float*>(smem), reinterpret_cast<float2*>(g.C) + cbase,
+                               [&](auto put) {
 #pragma unroll
         for (int bm = 0; bm < WM; ++bm)
 #pragma unroll
             for (int bn = 0; bn < WN; ++bn)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = (wm * WM + bm) * 16 + 4 * lg + r;
-                    if (i >= p0 && i < p0 + RP) fs[(i - p0) * TNR + (wn * WN + bn) * 16 + lr] = acc[bm][bn][r];
-                }
-        __syncthreads();
-        for (int x = tid; x < TM * TN; x += 256) {
-            int ml, nl;
-            const uint64_t off = decode_ep(g, x, ml, nl);
-            if (ml >= p0 && ml < p0 + RP) C[off] = Cs[(ml - p0) * TN + nl];
-        }
-        __syncthreads();
-    }
+                for (int r = 0; r < 4; ++r)
+                    put((wm * WM + bm) * 16 + 4 * lg + r, (wn * WN + bn) * 16 + lr, acc[bm][bn][r]);
+    });
 }
 
 __global__ void __launch_bounds__(256) k_fill(float* p, uint64_t n) {
@@ -781,7 +818,7 @@ hipError_t launch_valu(int storage, const GemmArgs& g, int R, hipStream_t s) {
 }
 
 hipError_t launch_stream(int storage, const GemmArgs& g, hipStream_t s) {
-    if (g.k_log > 4 || g.n_log > 4 || g.k_log + g.n_log > 6) return hipErrorInvalidValue;
+    if (g.k_log > 4 || g.n_log > 4) return hipErrorInvalidValue;
     if (storage == ST_C128) {
         const uint64_t blocks = std::max<uint64_t>(1, (1ull << g.m_log) / 256);
         if (g.m_log < 8) return hipErrorInvalidValue;

@@ -1,0 +1,52 @@
+"""Short run of the benchmark's launch sequence for profilers.
+
+Plans the 40-qubit workload exactly as bench.py does (same seed, restarts,
+slicing, autotuning), then contracts `--groups` launch groups (2^b slices
+each) with the same kernels, plus one plain device-to-device copy of
+`--copy-mib` MiB through torch.  Under `rocprofv3 --pmc FETCH_SIZE` (or
+WRITE_SIZE) the copy's counter reading against its known size gives the
+factor that turns the counter into HBM bytes.
+
+    rocprofv3 --kernel-trace --stats -d DIR -- python3 -m paper_2103_03074_amd.profile_run
+    rocprofv3 --pmc FETCH_SIZE -d DIR -- python3 -m paper_2103_03074_amd.profile_run --groups 2
+"""
+
+import argparse
+import sys
+
+SLICE_EDGES = {"c3_5x8_m16": 16, "c2_5x5_m16": 8}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--workload", default="c3_5x8_m16")
+    ap.add_argument("--prec", default="c64")
+    ap.add_argument("--groups", type=int, default=8)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--restarts", type=int, default=16)
+    args = ap.parse_args()
+    import torch
+    import rqc
+    from . import tn, runtime
+    torch.cuda.set_device(0)
+    w = rqc.workload(args.workload)
+    p = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], prec=args.prec, restarts=args.restarts,
+                n_slice_edges=SLICE_EDGES.get(args.workload, -1), seed=0)
+    s = p.stats()
+    ws = runtime.workspace(p)
+    acc = runtime.accumulator(p)
+    p.autotune(ws, acc, None, reps=5)
+    acc.zero_()
+    per = 2 ** s["batch_log2"]
+    p.contract_slices(ws, acc, 0, per * args.groups)
+    n = args.copy_mib << 18                      # float32 elements
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"profile_run: {args.workload} {args.prec}, {args.groups} launch groups of {per} slices, "
+          f"copy of {args.copy_mib} MiB", file=sys.stderr, flush=True)
+
+
+if __name__ == "__main__":
+    main()
