@@ -64,12 +64,31 @@ def dominant_kernel(profile, prec):
         ach = a["bytes"] / sec / 1e9
         rec = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS}
     rec.update({"kernel": name, "launches": a["launches"], "avg_launch_us": a["ms"] * 1e3 / max(1, a["launches"]),
+                "bytes_per_launch": a["bytes"] / max(1, a["launches"]),
                 "share_of_gpu_time": a["ms"] / max(1e-12, sum(v["ms"] for v in agg.values())),
                 "traffic": None})
     table = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
                  "TFLOP/s": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),
                  "GB/s": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in agg.items()}
     return rec, table
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE + WRITE_SIZE, calibrated against a
+    plain copy), or None when there is none or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, "paper_2103_03074_amd", "csrc", "kernels.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("kernels_source_sha256") != sha or kernel not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel]["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(w, plan, budget_s=30.0):
@@ -117,6 +136,8 @@ def main():
     ap.add_argument("--compare", default="", help="second precision timed on the same workload")
     ap.add_argument("--restarts", type=int, default=16)
     ap.add_argument("--batch-log2", type=int, default=-1)
+    ap.add_argument("--branch-merge", type=int, default=1,
+                    help="re-tune the tree for estimated time (merges small branches first)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
@@ -137,7 +158,8 @@ def main():
     def make(prec):
         t0 = time.perf_counter()
         p = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], prec=prec, restarts=args.restarts,
-                    n_slice_edges=SLICE_EDGES.get(args.workload, -1), batch_log2=args.batch_log2, seed=0)
+                    n_slice_edges=SLICE_EDGES.get(args.workload, -1), batch_log2=args.batch_log2, seed=0,
+                    branch_merge=args.branch_merge)
         return p, time.perf_counter() - t0
 
     def run(prec, steps, warmup, profile):
@@ -191,6 +213,8 @@ def main():
     tflops = 8.0 * main_run["cmacs"] / sec / 1e12
     amps_per_s = 2 ** s["n_open"] / sec
     roof, table = dominant_kernel(main_run["prof"], args.prec)
+    roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
+    roof["algorithmic_bytes_per_launch"] = roof.pop("bytes_per_launch")
     out = {
         "metric": METRIC, "value": tflops, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -198,7 +222,7 @@ def main():
         "config": {"workload": args.workload, "description": WORKLOAD_TEXT.get(args.workload, args.workload),
                    "n_slices": s["n_slices"], "slices_per_launch_sequence": 2 ** s["batch_log2"],
                    "largest_intermediate_log2": s["max_log2_size"], "restarts": args.restarts,
-                   "autotuned_shapes": main_run["n_tuned"], "launch": "eager with per-step HIP events"},
+                   "autotuned_shapes": main_run["n_tuned"], "branch_merge": args.branch_merge, "launch": "eager with per-step HIP events"},
         "pct_mfma_peak": 100.0 * tflops / PEAK_TFLOPS[args.prec],
         "amplitudes_per_s": amps_per_s,
         "complex_macs_per_step": main_run["cmacs"],

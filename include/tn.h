@@ -126,8 +126,8 @@ typedef struct {
     double bytes_per_batch;
     uint64_t workspace_bytes;     /* minimum ws_bytes for tn_contract_slices */
     uint64_t tail_workspace_bytes;/* minimum ws_bytes for tn_amplitudes */
-    int32_t n_dense_steps;        /* steps run on MFMA tiles */
-    int32_t n_small_steps;        /* steps run on the streaming VALU kernel */
+    int32_t n_dense_steps;        /* steps run on MFMA (tiled or skinny) */
+    int32_t n_small_steps;        /* steps run on the VALU kernels (tile, split-K, streaming) */
     int32_t cost_model_used;      /* 0 FLOP count, 1 learned model, 2 learned model asked but
                                      outside its training support (FLOP count used) */
     int32_t n_candidates;         /* candidate trees/slicings ranked */
@@ -213,7 +213,8 @@ tn_status tn_xeb(const double* d_amps, int32_t n_open, int32_t n_qubits, double 
  * elapsed times. */
 typedef struct {
     int32_t m_log, n_log, k_log, b_log;   /* step shape C[b,m,n] = sum_k A[k,b,m] B[k,b,n] */
-    int32_t kernel, tile;                 /* 0 VALU streaming, 1 MFMA tile, 2 split-K; tile id */
+    int32_t kernel, tile;                 /* 0 VALU tile, 1 MFMA tile, 2 split-K, 3 VALU streaming,
+                                             4 skinny MFMA; tile id */
     double cmacs;                         /* complex multiply-adds per launch */
     double bytes;                         /* algorithmic bytes per launch (A + B + C) */
     double total_ms;                      /* summed GPU time of this step's launches */
@@ -251,7 +252,8 @@ typedef struct tn_mlp_s* tn_mlp_t;
 #define TN_STEP_FEATURES 12
 
 /* Features of one step (shape logs, operand and output logs, log work, log
- * bytes at the plan's storage width, kernel class one-hot), written to
+ * bytes at the plan's storage width, kernel class flags: MFMA, VALU tile,
+ * split-K; the streaming kernel has none set), written to
  * out[TN_STEP_FEATURES]. */
 tn_status tn_step_features(int32_t m_log, int32_t n_log, int32_t k_log, int32_t b_log, int32_t kernel,
                            tn_precision prec, float* out);

@@ -119,6 +119,10 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
         g.tk = std::min(kMfmaTiles[st.tile].tk_max_log, st.k_log);
     } else if (st.kernel == K_STREAM) {
         g.tm = g.tn = g.tk = 0;
+    } else if (st.kernel == K_SKINNY) {
+        g.tm = 5;   // each wave stages 32 rows x 16 columns of C at a time
+        g.tn = 4;
+        g.tk = st.k_log;
     } else {
         const int m = st.m_log, n = st.n_log;
         g.split_log = st.kernel == K_SPLITK ? st.splitk_log : 0;
@@ -153,6 +157,14 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
     for (size_t i = 0; i < ep.size(); ++i) {
         g.ep_pos[i] = (uint8_t)ep[i].first;
         g.ep_src[i] = (uint8_t)ep[i].second;
+    }
+    if (st.kernel == K_SKINNY) {
+        if (name)
+            *name = "k_skinny<" + std::to_string(1 << std::min(st.k_log, 6)) + "," +
+                    std::to_string(1 << std::max(0, st.n_log - 4)) + ">";
+        hipError_t e = launch_skinny(g, s);
+        if (e != hipSuccess) return std::string("skinny launch: ") + hipGetErrorString(e);
+        return "";
     }
     if (name) {
         static const char* tile_names[] = {"<4,4,2,2", "<2,2,2,2", "<2,2,4,1", "<1,1,4,1", "<4,1,4,1"};
@@ -449,6 +461,7 @@ std::vector<Candidate> candidates(const Step& st, tn_precision prec) {
     if (mfma_capable(prec) && st.m_log >= 4 && st.n_log >= 3 && st.k_log >= 1)
         for (int t = 0; t < kNumMfmaTiles; ++t)
             if (kMfmaTiles[t].tm_log <= st.m_log && kMfmaTiles[t].tn_log <= st.n_log) c.push_back({K_MFMA, t, 0});
+    if (skinny_ok(st.m_log, st.n_log, st.k_log, st.b_log, prec)) c.push_back({K_SKINNY, 0, 0});
     c.push_back({K_SMALL, 0, 0});
     if (st.k_log <= 4 && st.n_log <= 4 && st.m_log >= (prec == TN_C128 ? 8 : 9) &&
         st.b_log <= 16)

@@ -463,6 +463,117 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
     });
 }
 
+// ------------------------------------------------------- skinny MFMA
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Big-times-small steps with N = 16..64 and K = 2..64 complex (the steps that
+// dominate once small branches are merged, appendix B): HBM-bound, so A is
+// streamed from global memory straight into MFMA operands and read once.
+//
+// v_mfma_f32_32x32x2f32 takes two real k per instruction.  Lane l holds row
+// r = l & 31 of A for real k index h = l >> 5, and one 8-byte load per lane
+// fetches the complex A[k0 + h][m0 + r]: its real parts feed one MFMA and its
+// imaginary parts a second one, against the matching rows of the 2x2 real
+// expansion of B:
+//     re A:  [Re B, Im B]  (real columns 2n, 2n+1)
+//     im A:  [-Im B, Re B]
+// B (K x N complex) sits in LDS for the whole block; the output column j of a
+// 32-column MFMA block is complex column j >> 1, component j & 1.  Each wave
+// owns 32 rows of C at a time; every 16-column slab is staged in LDS (rows
+// padded to 17 complex) and written in C-address order with the decode split
+// into a per-lane part and a per-iteration part (the decode is additive over
+// bits).  The block walks 128-row tiles of one batch entry with a grid
+// stride; the A fragments of the next tile are loaded while the current one
+// is multiplied.
+template <int KT, int NB>
+__global__ void __launch_bounds__(256) k_skinny(GemmArgs g) {
+    constexpr int N = 16 * NB;
+    constexpr int KP = KT / 2;              // complex k pairs
+    constexpr int CS = 17;                  // staged row stride (complex)
+    __shared__ __attribute__((aligned(16))) float2 Bs[KT * N];
+    __shared__ __attribute__((aligned(16))) float2 Cs[4][32 * CS];
+    const uint64_t beta = blockIdx.y;
+    const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
+    const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
+                      (beta << g.m_log);
+    const float2* B = reinterpret_cast<const float2*>(g.B) + slice_offset(g.d_slice, g.sb_n, g.sb_bit, g.sb_pos) +
+                      (beta << g.n_log);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int r = lane & 31, h = lane >> 5;
+    for (int e = tid; e < KT * N; e += 256) Bs[e] = B[(uint64_t)(e / N) * sBk + (e % N)];
+    // per-lane part of the epilogue decode (tile bits 0..5 of the C-order index)
+    uint64_t off_lo = 0;
+    int src_lo = 0;
+    for (int i = 0; i < 6 && i < g.ep_n; ++i)
+        if ((lane >> i) & 1) {
+            off_lo |= 1ull << g.ep_pos[i];
+            const int sb = g.ep_src[i];
+            src_lo += sb < 32 ? CS << sb : 1 << (sb - 32);
+        }
+    __syncthreads();
+    const uint64_t tiles = 1ull << (g.m_log - 7);
+    uint64_t t = blockIdx.x;
+    float2 a[KP], an[KP];
+    auto load = [&](float2* dst, uint64_t tt) {
+        const float2* src = A + tt * 128 + w * 32 + r + (uint64_t)h * sAk;
+#pragma unroll
+        for (int p = 0; p < KP; ++p) dst[p] = src[(uint64_t)(2 * p) * sAk];
+    };
+    if (t < tiles) load(a, t);
+    float mx = 0.f;
+    float2* C = reinterpret_cast<float2*>(g.C);
+    float* cs = reinterpret_cast<float*>(Cs[w]);
+    for (; t < tiles; t += gridDim.x) {
+        if (t + gridDim.x < tiles) load(an, t + gridDim.x);
+        floatx16 acc[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const float2 b = Bs[(2 * p + h) * N + nb * 16 + (r >> 1)];
+                const float b_re = (r & 1) ? b.y : b.x;
+                const float b_im = (r & 1) ? b.x : -b.y;
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].x, b_re, acc[nb], 0, 0, 0);
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].y, b_im, acc[nb], 0, 0, 0);
+            }
+        }
+        const uint64_t m0 = t * 128 + w * 32;
+        const uint64_t cbase = deposit(m0, g.cpm, 5, g.m_log) + deposit(beta, g.cpb, 0, g.b_log);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = 8 * (v >> 2) + 4 * h + (v & 3);
+                cs[row * (2 * CS) + r] = acc[nb][v];
+                mx = fmaxf(mx, fabsf(acc[nb][v]));
+            }
+            __syncthreads();
+            const uint64_t cb = cbase + deposit((uint64_t)nb << 4, g.cpn, 4, g.n_log);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                uint64_t off_hi = 0;
+                int src_hi = 0;
+                for (int i = 6; i < g.ep_n; ++i)
+                    if ((j >> (i - 6)) & 1) {
+                        off_hi |= 1ull << g.ep_pos[i];
+                        const int sb = g.ep_src[i];
+                        src_hi += sb < 32 ? CS << sb : 1 << (sb - 32);
+                    }
+                C[cb + (off_lo | off_hi)] = Cs[w][src_lo + src_hi];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int p = 0; p < KP; ++p) a[p] = an[p];
+    }
+    if (g.cmax) tile_max_atomic(mx, g.cmax);
+}
+
 // ------------------------------------------------- low-precision MFMA
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
@@ -828,6 +939,39 @@ hipError_t launch_stream(int storage, const GemmArgs& g, hipStream_t s) {
         const uint64_t blocks = (1ull << g.m_log) / 512;
         hipLaunchKernelGGL((k_stream<float2, 2>), dim3((unsigned)blocks, 1u << g.b_log), dim3(256), 0, s, g);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_skinny(const GemmArgs& g, hipStream_t s) {
+    if (g.n_log < 4 || g.n_log > 6 || g.k_log < 1 || g.k_log > 6 || g.k_log + g.n_log > 12 || g.m_log < 7 ||
+        g.b_log > 16 || g.tm != 5 || g.tn != 4 || g.ep_n != 9)
+        return hipErrorInvalidValue;
+    const uint64_t tiles = 1ull << (g.m_log - 7);
+    // enough blocks to fill the chip several times, each walking several tiles
+    const int want_log = std::max(0, 12 - g.b_log);
+    const unsigned bx = (unsigned)std::min<uint64_t>(tiles, 1ull << want_log);
+    const dim3 grid(bx, 1u << g.b_log);
+#define TN_SK(KT, NB) hipLaunchKernelGGL((k_skinny<KT, NB>), grid, dim3(256), 0, s, g)
+#define TN_SK_N(KT)                    \
+    switch (g.n_log) {                 \
+        case 4: TN_SK(KT, 1); break;   \
+        case 5: TN_SK(KT, 2); break;   \
+        default: TN_SK(KT, 4); break;  \
+    }
+    switch (g.k_log) {
+        case 1: TN_SK_N(2); break;
+        case 2: TN_SK_N(4); break;
+        case 3: TN_SK_N(8); break;
+        case 4: TN_SK_N(16); break;
+        case 5: TN_SK_N(32); break;
+        default:
+            if (g.n_log == 6) TN_SK(64, 4);
+            else if (g.n_log == 5) TN_SK(64, 2);
+            else TN_SK(64, 1);
+            break;
+    }
+#undef TN_SK_N
+#undef TN_SK
     return hipGetLastError();
 }
 

@@ -25,6 +25,12 @@ constexpr int kNumMfmaTiles = sizeof(kMfmaTiles) / sizeof(kMfmaTiles[0]);
 
 inline bool mfma_capable(tn_precision p) { return p != TN_C128; }
 
+// Skinny MFMA kernel: N = 16..64 complex columns, K = 2..64, B of at most 4096
+// complex elements (held in LDS), 128-row tiles, complex64 storage.
+inline bool skinny_ok(int m, int n, int k, int b, tn_precision prec) {
+    return mfma_capable(prec) && n >= 4 && n <= 6 && k >= 1 && k <= 6 && k + n <= 12 && m >= 7 && b <= 16;
+}
+
 // Choose the kernel class and tile for C[b,m,n] = sum_k A[k,b,m] B[k,b,n]
 // (all sizes log2).  Dense steps go to MFMA tiles; steps whose output is tiny
 // but whose contracted dimension is long are split along K; everything else
@@ -35,6 +41,11 @@ inline void choose_kernel(int m, int n, int k, int b, tn_precision prec, int& ke
     kernel = 0;
     tile = 0;
     splitk_log = 0;
+    // many rows against a small B: stream A once through the skinny kernel
+    if (skinny_ok(m, n, k, b, prec) && m + b >= 14) {
+        kernel = 4;
+        return;
+    }
     if (mfma_capable(prec) && m >= 6 && n >= 3 && k >= 2) {
         int best = -1;
         for (int t = 0; t < kNumMfmaTiles; ++t) {

@@ -24,6 +24,8 @@ def main():
     ap.add_argument("--groups", type=int, default=8)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--restarts", type=int, default=16)
+    ap.add_argument("--branch-merge", type=int, default=1)
+    ap.add_argument("--tune-cache", default="", help="autotuner cache (read, and extended)")
     args = ap.parse_args()
     import torch
     import rqc
@@ -31,11 +33,11 @@ def main():
     torch.cuda.set_device(0)
     w = rqc.workload(args.workload)
     p = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], prec=args.prec, restarts=args.restarts,
-                n_slice_edges=SLICE_EDGES.get(args.workload, -1), seed=0)
+                n_slice_edges=SLICE_EDGES.get(args.workload, -1), seed=0, branch_merge=args.branch_merge)
     s = p.stats()
     ws = runtime.workspace(p)
     acc = runtime.accumulator(p)
-    p.autotune(ws, acc, None, reps=5)
+    p.autotune(ws, acc, args.tune_cache or None, reps=5)
     acc.zero_()
     per = 2 ** s["batch_log2"]
     p.contract_slices(ws, acc, 0, per * args.groups)

@@ -203,9 +203,9 @@ def test_xeb_on_device_matches_oracle(c2_state):
 
 # --- full bench shape: 40-qubit 5x8 grid, 16 cycles, 16 open, 2^16 slices ---
 
-def _c3_plan(w, **kw):
+def _c3_plan(w, branch_merge=1, **kw):
     # same planner options as bench.py
-    return _plan(w, n_slice_edges=16, restarts=16, seed=0, **kw)
+    return _plan(w, n_slice_edges=16, restarts=16, seed=0, branch_merge=branch_merge, **kw)
 
 
 # Product-state amplitudes span a wide dynamic range; at this depth numpy's
@@ -240,13 +240,18 @@ def test_c3_product_circuit_closed_form_full_shape(prec, tol):
     assert _rel(got, ref) < tol
 
 
-def test_c3_random_circuit_slice_vs_oracle():
+@pytest.mark.parametrize("branch_merge", [0, 1])
+def test_c3_random_circuit_slice_vs_oracle(branch_merge):
     """One slice of the bench workload against the oracle's complex128
     contraction (the plan's tree is only the oracle's schedule; results do not
-    depend on the order)."""
+    depend on the order).  Both trees run steps on the skinny MFMA kernel
+    (N of 16 to 64, with and without batch legs); the unmerged one also on
+    the streaming kernel."""
     w = rqc.workload("c3_5x8_m16")
-    p = _c3_plan(w)
+    p = _c3_plan(w, branch_merge=branch_merge)
     ex = p.export()
+    kinds = {st["kernel"] for st in ex["steps"]}
+    assert 4 in kinds and (branch_merge or 3 in kinds)
     sliced = [tuple(e) for e in ex["sliced"]]
     tree = list(zip(ex["lhs"], ex["rhs"]))
     net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
