@@ -90,13 +90,19 @@ struct TileIndex {
 };
 
 __device__ __forceinline__ TileIndex tile_index(const GemmArgs& g) {
-    uint64_t t = blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+    const uint64_t nblk = (uint64_t)gridDim.x * gridDim.y;   // one block per tile (a power of two)
+    const uint64_t bid = blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+    // Workgroups go round-robin to the 8 XCDs, each with its own L2: XCD x
+    // takes the contiguous logical range [x, x + 1) * nblk / 8, and N tiles
+    // vary fastest, so the blocks sharing one A row block run back to back on
+    // one L2 and A is fetched from HBM about once.
+    uint64_t t = (nblk & 7) == 0 ? (bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
     const int mtb = g.m_log - g.tm, ntb = g.n_log - g.tn;
     TileIndex ti;
-    ti.m0 = (t & ((1ull << mtb) - 1)) << g.tm;
-    t >>= mtb;
     ti.n0 = (t & ((1ull << ntb) - 1)) << g.tn;
     t >>= ntb;
+    ti.m0 = (t & ((1ull << mtb) - 1)) << g.tm;
+    t >>= mtb;
     ti.beta = t & ((1ull << g.b_log) - 1);
     t >>= g.b_log;
     ti.split = t;
@@ -576,6 +582,8 @@ __global__ void __launch_bounds__(256) k_skinny(GemmArgs g) {
 
 // ------------------------------------------------- low-precision MFMA
 
+constexpr int kRowPad = 36;   // words per staged row: 32 k + 4 (bank spread, 16-byte aligned)
+
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -620,8 +628,11 @@ __device__ __forceinline__ int scale_exp(const float* mx) {
 // producers' max (exact, so nothing underflows FP16) and split into hi/lo
 // FP16 pairs: x = hi + 2^-11 lo, product = hi*hi + 2^-11 (hi*lo + lo*hi)
 // (split mode; the single-term modes use hi only).  The complex product is
-// 4 real products as in the FP32 kernel: A' = [Re A | Im A] interleaved,
-// B expanded to [[re, im], [-im, re]] while the fragment is built.
+// 4 real products as in the FP32 kernel: A' = [Re A | Im A] interleaved (one
+// packed (re, im) word per complex k), B' = [[re, im], [-im, re]] (real
+// column 2n holds (re, -im) words, column 2n+1 (im, re)).  Both are staged in
+// LDS k-fastest, one row per m or real column, padded to 36 words, so a
+// lane's eight k-slots (four words) are one 16-byte read.
 template <int WM, int WN, int WAVES_M, int WAVES_N, int MODE>
 __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
     constexpr int TM = WAVES_M * WM * 16;
@@ -630,14 +641,13 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
     constexpr int TK = 32;                  // complex k per chunk = two MFMA k-steps (32 real each)
     constexpr bool SPLIT = MODE == LP_SPLIT_FP16;
     constexpr int PLANES = SPLIT ? 2 : 1;
-    constexpr int AB_WORDS = PLANES * TK * (TM + TN);
+    constexpr int AB_WORDS = PLANES * (TM + TNR) * kRowPad;
     using L = MfmaLds<TM, TNR, AB_WORDS>;
     __shared__ __attribute__((aligned(16))) uint32_t smem[L::FLOATS];
-    // LDS planes stored [k][m] / [k][n]: one packed (re, im) word per element
-    uint32_t* Ahi = smem;
-    uint32_t* Alo = Ahi + TK * TM;
-    uint32_t* Bhi = smem + PLANES * TK * TM;
-    uint32_t* Blo = Bhi + TK * TN;
+    uint32_t* Ahi = smem;                               // [TM][kRowPad]
+    uint32_t* Alo = Ahi + TM * kRowPad;
+    uint32_t* Bhi = smem + PLANES * TM * kRowPad;       // [TNR][kRowPad]
+    uint32_t* Blo = Bhi + TNR * kRowPad;
     const TileIndex ti = tile_index(g);
     const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
     const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
@@ -683,66 +693,67 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
         for (int i = 0; i < PA; ++i) {
             const int e = tid + 256 * i;
             if (e < TK * TM) {
+                const int kk = e / TM, mm = e % TM;
                 uint32_t hi, lo;
                 split_pack<MODE>(ra[i], sa, hi, lo);
-                Ahi[e] = hi;
-                if constexpr (SPLIT) Alo[e] = lo;
+                Ahi[mm * kRowPad + kk] = hi;
+                if constexpr (SPLIT) Alo[mm * kRowPad + kk] = lo;
             }
         }
 #pragma unroll
         for (int i = 0; i < PB; ++i) {
             const int e = tid + 256 * i;
             if (e < TK * TN) {
+                const int kk = e / TN, nn = e % TN;
                 uint32_t hi, lo;
                 split_pack<MODE>(rb[i], sb, hi, lo);
-                Bhi[e] = hi;
-                if constexpr (SPLIT) Blo[e] = lo;
+                Bhi[(2 * nn) * kRowPad + kk] = bexp(hi, 0);
+                Bhi[(2 * nn + 1) * kRowPad + kk] = bexp(hi, 1);
+                if constexpr (SPLIT) {
+                    Blo[(2 * nn) * kRowPad + kk] = bexp(lo, 0);
+                    Blo[(2 * nn + 1) * kRowPad + kk] = bexp(lo, 1);
+                }
             }
         }
         __syncthreads();
         if (k0 + TK < K) load_chunk(k0 + TK);
 #pragma unroll
         for (int ks = 0; ks < TK; ks += 16) {
-        uint4 ah[WM], al[SPLIT ? WM : 1], bh[WN], bl[SPLIT ? WN : 1];
+            uint4 ah[WM], al[SPLIT ? WM : 1], bh[WN], bl[SPLIT ? WN : 1];
 #pragma unroll
-        for (int bm = 0; bm < WM; ++bm) {
-            const int row = (wm * WM + bm) * 16 + lr;
-            const uint32_t* p = Ahi + (ks + 4 * lg) * TM + row;
-            ah[bm] = uint4{p[0], p[TM], p[2 * TM], p[3 * TM]};
-            if constexpr (SPLIT) {
-                const uint32_t* q = Alo + (ks + 4 * lg) * TM + row;
-                al[bm] = uint4{q[0], q[TM], q[2 * TM], q[3 * TM]};
+            for (int bm = 0; bm < WM; ++bm) {
+                const int o = ((wm * WM + bm) * 16 + lr) * kRowPad + ks + 4 * lg;
+                ah[bm] = *reinterpret_cast<const uint4*>(Ahi + o);
+                if constexpr (SPLIT) al[bm] = *reinterpret_cast<const uint4*>(Alo + o);
             }
-        }
-#pragma unroll
-        for (int bn = 0; bn < WN; ++bn) {
-            const int jr = (wn * WN + bn) * 16 + lr;
-            const int odd = jr & 1;
-            const uint32_t* p = Bhi + (ks + 4 * lg) * TN + (jr >> 1);
-            bh[bn] = uint4{bexp(p[0], odd), bexp(p[TN], odd), bexp(p[2 * TN], odd), bexp(p[3 * TN], odd)};
-            if constexpr (SPLIT) {
-                const uint32_t* q = Blo + (ks + 4 * lg) * TN + (jr >> 1);
-                bl[bn] = uint4{bexp(q[0], odd), bexp(q[TN], odd), bexp(q[2 * TN], odd), bexp(q[3 * TN], odd)};
-            }
-        }
-#pragma unroll
-        for (int bm = 0; bm < WM; ++bm)
 #pragma unroll
             for (int bn = 0; bn < WN; ++bn) {
-                if constexpr (MODE == LP_BF16) {
-                    acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bh[bn]), acc[bm][bn], 0, 0, 0);
-                } else {
-                    acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                        __builtin_bit_cast(half8, ah[bm]), __builtin_bit_cast(half8, bh[bn]), acc[bm][bn], 0, 0, 0);
-                    if constexpr (SPLIT) {
-                        accx[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                            __builtin_bit_cast(half8, ah[bm]), __builtin_bit_cast(half8, bl[bn]), accx[bm][bn], 0, 0, 0);
-                        accx[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                            __builtin_bit_cast(half8, al[bm]), __builtin_bit_cast(half8, bh[bn]), accx[bm][bn], 0, 0, 0);
+                const int o = ((wn * WN + bn) * 16 + lr) * kRowPad + ks + 4 * lg;
+                bh[bn] = *reinterpret_cast<const uint4*>(Bhi + o);
+                if constexpr (SPLIT) bl[bn] = *reinterpret_cast<const uint4*>(Blo + o);
+            }
+#pragma unroll
+            for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+                for (int bn = 0; bn < WN; ++bn) {
+                    if constexpr (MODE == LP_BF16) {
+                        acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bh[bn]), acc[bm][bn], 0,
+                            0, 0);
+                    } else {
+                        acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                            __builtin_bit_cast(half8, ah[bm]), __builtin_bit_cast(half8, bh[bn]), acc[bm][bn], 0, 0,
+                            0);
+                        if constexpr (SPLIT) {
+                            accx[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                __builtin_bit_cast(half8, ah[bm]), __builtin_bit_cast(half8, bl[bn]), accx[bm][bn],
+                                0, 0, 0);
+                            accx[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                __builtin_bit_cast(half8, al[bm]), __builtin_bit_cast(half8, bh[bn]), accx[bm][bn],
+                                0, 0, 0);
+                        }
                     }
                 }
-            }
         }
         __syncthreads();
     }

@@ -10,7 +10,8 @@ with `--pmc FETCH_SIZE` and one with `--pmc WRITE_SIZE`.  It writes
   profiling driver ends with (`--copy-mib`, read once and written once).
 
 The JSON records the SHA-256 of the kernel source the counters were taken
-with, so a reader can tell when the figures are stale.
+with (`--source-sha-file`, written next to the databases by the profiling
+commands), so a reader can tell when the figures are stale.
 
     python -m paper_2103_03074_amd.profile_summary --trace T.db --fetch F.db --write W.db \\
         --copy-mib 1024 --out profiles/c3_5x8_m16 --command "..."
@@ -76,6 +77,8 @@ def main():
     ap.add_argument("--out", required=True, help="output prefix")
     ap.add_argument("--command", default="", help="the profiling commands, recorded verbatim")
     ap.add_argument("--title", default="")
+    ap.add_argument("--source-sha-file", default="",
+                    help="sha256sum output for kernels.hip written on the profiled machine")
     args = ap.parse_args()
 
     tr = trace_table(args.trace)
@@ -97,8 +100,12 @@ def main():
         raise SystemExit("the calibration copy is missing from the counter runs")
     f_fac = copy_kib / fe[COPY_KERNEL][0]
     w_fac = copy_kib / wr[COPY_KERNEL][0]
+    sha = kernel_source_sha()
+    if args.source_sha_file:
+        with open(args.source_sha_file) as f:
+            sha = f.read().split()[0]
     res = {"copy_mib": args.copy_mib, "fetch_factor": f_fac, "write_factor": w_fac,
-           "kernels_source_sha256": kernel_source_sha(), "kernels": {}}
+           "kernels_source_sha256": sha, "kernels": {}}
     lines = [f"# HBM traffic per dispatch: {args.title}", "", "Commands:", ""]
     lines += ["    " + c for c in args.command.split(" ;; ") if c]
     lines += ["",
