@@ -126,7 +126,7 @@ typedef struct {
     double bytes_per_batch;
     uint64_t workspace_bytes;     /* minimum ws_bytes for tn_contract_slices */
     uint64_t tail_workspace_bytes;/* minimum ws_bytes for tn_amplitudes */
-    int32_t n_dense_steps;        /* steps run on MFMA (tiled or skinny) */
+    int32_t n_dense_steps;        /* steps run on MFMA (tiled, skinny or panel) */
     int32_t n_small_steps;        /* steps run on the VALU kernels (tile, split-K, streaming) */
     int32_t cost_model_used;      /* 0 FLOP count, 1 learned model, 2 learned model asked but
                                      outside its training support (FLOP count used) */
@@ -214,7 +214,7 @@ tn_status tn_xeb(const double* d_amps, int32_t n_open, int32_t n_qubits, double 
 typedef struct {
     int32_t m_log, n_log, k_log, b_log;   /* step shape C[b,m,n] = sum_k A[k,b,m] B[k,b,n] */
     int32_t kernel, tile;                 /* 0 VALU tile, 1 MFMA tile, 2 split-K, 3 VALU streaming,
-                                             4 skinny MFMA; tile id */
+                                             4 skinny MFMA, 5 panel MFMA; tile id */
     double cmacs;                         /* complex multiply-adds per launch */
     double bytes;                         /* algorithmic bytes per launch (A + B + C) */
     double total_ms;                      /* summed GPU time of this step's launches */

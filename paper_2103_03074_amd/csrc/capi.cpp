@@ -352,7 +352,7 @@ tn_status tn_plan_autotune(tn_plan_t p, void* d_workspace, size_t ws_bytes, doub
         // kernel counts in the stats follow the new choices
         p->plan.stats.n_dense_steps = p->plan.stats.n_small_steps = 0;
         for (const tn::Step& st : p->plan.steps)
-            (st.kernel == tn::K_MFMA || st.kernel == tn::K_SKINNY ? p->plan.stats.n_dense_steps : p->plan.stats.n_small_steps)++;
+            (st.kernel == tn::K_MFMA || st.kernel == tn::K_SKINNY || st.kernel == tn::K_PANEL ? p->plan.stats.n_dense_steps : p->plan.stats.n_small_steps)++;
         return TN_OK;
     } catch (const std::bad_alloc&) {
         return fail(TN_ENOMEM, "host allocation failed");

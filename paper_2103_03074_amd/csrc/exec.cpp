@@ -123,6 +123,10 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
         g.tm = 5;   // each wave stages 32 rows x 16 columns of C at a time
         g.tn = 4;
         g.tk = st.k_log;
+    } else if (st.kernel == K_PANEL) {
+        g.tm = 7;   // the block stages 128 rows x 16 columns of C at a time
+        g.tn = 4;   // (the epilogue decode); the tile width is set below
+        g.tk = panel_kc_log(st.tile);
     } else {
         const int m = st.m_log, n = st.n_log;
         g.split_log = st.kernel == K_SPLITK ? st.splitk_log : 0;
@@ -157,6 +161,15 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
     for (size_t i = 0; i < ep.size(); ++i) {
         g.ep_pos[i] = (uint8_t)ep[i].first;
         g.ep_src[i] = (uint8_t)ep[i].second;
+    }
+    if (st.kernel == K_PANEL) {
+        g.tn = panel_tn_log(st.tile);
+        if (name)
+            *name = std::string("k_panel<") + (panel_kc_log(st.tile) == 5 ? "32," : "16,") +
+                    (panel_tn_log(st.tile) == 6 ? "4>" : "2>");
+        hipError_t e = launch_panel(st.tile, g, s);
+        if (e != hipSuccess) return std::string("panel launch: ") + hipGetErrorString(e);
+        return "";
     }
     if (st.kernel == K_SKINNY) {
         if (name)
@@ -462,6 +475,8 @@ std::vector<Candidate> candidates(const Step& st, tn_precision prec) {
         for (int t = 0; t < kNumMfmaTiles; ++t)
             if (kMfmaTiles[t].tm_log <= st.m_log && kMfmaTiles[t].tn_log <= st.n_log) c.push_back({K_MFMA, t, 0});
     if (skinny_ok(st.m_log, st.n_log, st.k_log, st.b_log, prec)) c.push_back({K_SKINNY, 0, 0});
+    for (int t = 0; t < kNumPanelTiles; ++t)
+        if (panel_ok(st.m_log, st.n_log, st.k_log, st.b_log, prec, t)) c.push_back({K_PANEL, t, 0});
     c.push_back({K_SMALL, 0, 0});
     if (st.k_log <= 4 && st.n_log <= 4 && st.m_log >= (prec == TN_C128 ? 8 : 9) &&
         st.b_log <= 16)

@@ -580,6 +580,116 @@ __global__ void __launch_bounds__(256) k_skinny(GemmArgs g) {
     if (g.cmax) tile_max_atomic(mx, g.cmax);
 }
 
+// ------------------------------------------------------------ panel MFMA
+
+// Dense steps on the 32x32x2 FP32 MFMA with the operand scheme of k_skinny:
+// a block owns 128 rows (4 waves x 32) and 16 NB complex columns; K runs in
+// chunks of KC complex.  Each wave streams its A rows from global memory
+// straight into MFMA operands (the next chunk is loaded while the current
+// one is multiplied), the B chunk is staged in LDS through registers, and
+// the 128 x 16 output slabs are staged in LDS and written in C-address order
+// (tile bits m0..m6, n0..n3 in the epilogue decode).  Tiles are visited in
+// the XCD-aware order of tile_index (tm = 7, tn = 4 + log2 NB).
+template <int KC, int NB>
+__global__ void __launch_bounds__(256) k_panel(GemmArgs g) {
+    constexpr int N = 16 * NB;
+    constexpr int KP = KC / 2;
+    constexpr int CS = 17;
+    constexpr int PBN = KC * N / 256;       // B chunk elements per thread
+    __shared__ __attribute__((aligned(16))) float2 Bs[KC * N];
+    __shared__ __attribute__((aligned(16))) float2 Cs[128 * CS];
+    const TileIndex ti = tile_index(g);
+    const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
+    const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
+                      (ti.beta << g.m_log) + ti.m0;
+    const float2* B = reinterpret_cast<const float2*>(g.B) + slice_offset(g.d_slice, g.sb_n, g.sb_bit, g.sb_pos) +
+                      (ti.beta << g.n_log) + ti.n0;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int r = lane & 31, h = lane >> 5;
+    const uint64_t K = 1ull << g.k_log;
+    float2 a[KP], an[KP], bb[PBN];
+    auto load_a = [&](float2* dst, uint64_t k0) {
+        const float2* src = A + w * 32 + r + (k0 + h) * sAk;
+#pragma unroll
+        for (int p = 0; p < KP; ++p) dst[p] = src[(uint64_t)(2 * p) * sAk];
+    };
+    auto load_b = [&](uint64_t k0) {
+#pragma unroll
+        for (int i = 0; i < PBN; ++i) {
+            const int e = tid + 256 * i;
+            bb[i] = B[(k0 + e / N) * sBk + (e % N)];
+        }
+    };
+    floatx16 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
+    load_a(a, 0);
+    load_b(0);
+    for (uint64_t k0 = 0; k0 < K; k0 += KC) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PBN; ++i) Bs[tid + 256 * i] = bb[i];
+        __syncthreads();
+        if (k0 + KC < K) {
+            load_a(an, k0 + KC);
+            load_b(k0 + KC);
+        }
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const float2 b = Bs[(2 * p + h) * N + nb * 16 + (r >> 1)];
+                const float b_re = (r & 1) ? b.y : b.x;
+                const float b_im = (r & 1) ? b.x : -b.y;
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].x, b_re, acc[nb], 0, 0, 0);
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].y, b_im, acc[nb], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < KP; ++p) a[p] = an[p];
+    }
+    // epilogue: tile bits m0..m6, n0..n3 (ep arrays for tm = 7, tn = 4)
+    uint64_t off_lo = 0;
+    int src_lo = 0;
+    for (int i = 0; i < 8; ++i)
+        if ((tid >> i) & 1) {
+            off_lo |= 1ull << g.ep_pos[i];
+            const int sb = g.ep_src[i];
+            src_lo += sb < 32 ? CS << sb : 1 << (sb - 32);
+        }
+    float mx = 0.f;
+    const uint64_t cbase = deposit(ti.m0, g.cpm, 7, g.m_log) + deposit(ti.beta, g.cpb, 0, g.b_log);
+    float* cs = reinterpret_cast<float*>(Cs);
+    float2* C = reinterpret_cast<float2*>(g.C);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = w * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+            cs[row * (2 * CS) + r] = acc[nb][v];
+            mx = fmaxf(mx, fabsf(acc[nb][v]));
+        }
+        __syncthreads();
+        const uint64_t cb = cbase + deposit(ti.n0 + ((uint64_t)nb << 4), g.cpn, 4, g.n_log);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            uint64_t off_hi = 0;
+            int src_hi = 0;
+            for (int i = 8; i < g.ep_n; ++i)
+                if ((j >> (i - 8)) & 1) {
+                    off_hi |= 1ull << g.ep_pos[i];
+                    const int sb = g.ep_src[i];
+                    src_hi += sb < 32 ? CS << sb : 1 << (sb - 32);
+                }
+            C[cb + (off_lo | off_hi)] = Cs[src_lo + src_hi];
+        }
+    }
+    if (g.cmax) tile_max_atomic(mx, g.cmax);
+}
+
 // ------------------------------------------------- low-precision MFMA
 
 constexpr int kRowPad = 36;   // words per staged row: 32 k + 4 (bank spread, 16-byte aligned)
@@ -910,9 +1020,16 @@ uint64_t tile_blocks(const GemmArgs& g) {
     return 1ull << ((g.m_log - g.tm) + (g.n_log - g.tn) + g.b_log + g.split_log);
 }
 
+// A tile must fit the step: tile_index shifts by m_log - tm and n_log - tn.
+bool tile_fits(const GemmArgs& g) {
+    return g.tm >= 0 && g.tn >= 0 && g.tm <= g.m_log && g.tn <= g.n_log && g.split_log >= 0 &&
+           g.split_log <= g.k_log && (g.m_log - g.tm) + (g.n_log - g.tn) + g.b_log + g.split_log < 62;
+}
+
 }  // namespace
 
 hipError_t launch_valu(int storage, const GemmArgs& g, int R, hipStream_t s) {
+    if (!tile_fits(g)) return hipErrorInvalidValue;
     const size_t esz = storage == ST_C128 ? 16 : 8;
     const size_t ab = (size_t)((1 << g.tk) * ((1 << g.tm) + (1 << g.tn)));
     const size_t st = (size_t)1 << (g.tm + g.tn);
@@ -986,6 +1103,22 @@ hipError_t launch_skinny(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_panel(int tile, const GemmArgs& g, hipStream_t s) {
+    // tile: bit 0 -> KC = 16 (else 32), bit 1 -> NB = 2 (else 4)
+    const int kc_log = (tile & 1) ? 4 : 5, nb_log = (tile & 2) ? 1 : 2;
+    if (tile < 0 || tile > 3 || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) || g.k_log < kc_log ||
+        g.ep_n != 11 || g.split_log != 0)
+        return hipErrorInvalidValue;
+    const dim3 grid = grid_for(tile_blocks(g));
+    switch (tile) {
+        case 0: hipLaunchKernelGGL((k_panel<32, 4>), grid, dim3(256), 0, s, g); break;
+        case 1: hipLaunchKernelGGL((k_panel<16, 4>), grid, dim3(256), 0, s, g); break;
+        case 2: hipLaunchKernelGGL((k_panel<32, 2>), grid, dim3(256), 0, s, g); break;
+        default: hipLaunchKernelGGL((k_panel<16, 2>), grid, dim3(256), 0, s, g); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_splitk_reduce(int storage, const GemmArgs& g, hipStream_t s) {
     const uint64_t total = 1ull << (g.m_log + g.n_log + g.b_log);
     const dim3 grid = grid_for((total + 255) / 256);
@@ -1013,6 +1146,7 @@ hipError_t launch_fill(float* p, uint64_t n, hipStream_t s) {
 }
 
 hipError_t launch_mfma(int mode, int tile, const GemmArgs& g, hipStream_t s) {
+    if (!tile_fits(g)) return hipErrorInvalidValue;
     const dim3 grid = grid_for(tile_blocks(g));
     if (mode == LP_SPLIT_FP16) return launch_lp<LP_SPLIT_FP16>(tile, g, grid, s);
     if (mode == LP_FP16) return launch_lp<LP_FP16>(tile, g, grid, s);

@@ -50,6 +50,7 @@ enum Storage : int { ST_C64 = 0, ST_C128 = 1, ST_BF16 = 2 };
 hipError_t launch_valu(int storage, const GemmArgs& g, int R, hipStream_t s);
 hipError_t launch_stream(int storage, const GemmArgs& g, hipStream_t s);
 hipError_t launch_skinny(const GemmArgs& g, hipStream_t s);   // complex64 storage, FP32 MFMA
+hipError_t launch_panel(int tile, const GemmArgs& g, hipStream_t s);   // complex64, FP32 MFMA
 hipError_t launch_splitk_reduce(int storage, const GemmArgs& g, hipStream_t s);
 hipError_t launch_mfma(int mode, int tile, const GemmArgs& g, hipStream_t s);   // mode -1: FP32, else LpMode
 hipError_t launch_fill(float* p, uint64_t n, hipStream_t s);

@@ -112,7 +112,7 @@ void step_features(int m, int n, int k, int b, int kernel, int esize, float* f) 
     const double bytes = esize * (std::exp2((double)(m + k + b)) + std::exp2((double)(n + k + b)) +
                                   std::exp2((double)(m + n + b)));
     f[8] = (float)(std::log2(bytes) / 40.0);
-    f[9] = (kernel == 1 || kernel == 4) ? 1.f : 0.f;   // MFMA classes
+    f[9] = (kernel == 1 || kernel == 4 || kernel == 5) ? 1.f : 0.f;   // MFMA classes
     f[10] = kernel == 0 ? 1.f : 0.f;
     f[11] = kernel == 2 ? 1.f : 0.f;
 }

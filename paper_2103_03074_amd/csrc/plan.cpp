@@ -636,7 +636,7 @@ static void fill_stats(Plan& p) {
             per_batch += st.cmacs;
             bytes += st.bytes;
         }
-        if (st.kernel == K_MFMA || st.kernel == K_SKINNY) s.n_dense_steps++;
+        if (st.kernel == K_MFMA || st.kernel == K_SKINNY || st.kernel == K_PANEL) s.n_dense_steps++;
         else s.n_small_steps++;   // streaming, VALU tile and split-K
     }
     for (int c = p.tree.n_leaves; c < p.tree.n_nodes(); ++c)

@@ -84,7 +84,7 @@ double tree_time_estimate(const std::vector<Legs>& leaf_legs, const Tree& t, con
 Tree time_order_tree(int n_leaves);
 
 // Kernel classes a step can run on.
-enum StepKernel : int32_t { K_SMALL = 0, K_MFMA = 1, K_SPLITK = 2, K_STREAM = 3, K_SKINNY = 4 };
+enum StepKernel : int32_t { K_SMALL = 0, K_MFMA = 1, K_SPLITK = 2, K_STREAM = 3, K_SKINNY = 4, K_PANEL = 5 };
 
 // One pairwise step as executed: C[b, m, n] = sum_k A[k, b, m] * B[k, b, n].
 // A is stored [K legs | batch legs | M legs] from the most to the least

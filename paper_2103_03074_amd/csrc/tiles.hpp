@@ -31,6 +31,16 @@ inline bool skinny_ok(int m, int n, int k, int b, tn_precision prec) {
     return mfma_capable(prec) && n >= 4 && n <= 6 && k >= 1 && k <= 6 && k + n <= 12 && m >= 7 && b <= 16;
 }
 
+// Panel MFMA kernel (complex64, FP32): 128 rows x 16 NB columns per block, K
+// in chunks of KC.  Tile id: bit 0 -> KC = 16 (else 32), bit 1 -> NB = 2 (else 4).
+constexpr int kNumPanelTiles = 4;
+inline int panel_kc_log(int tile) { return (tile & 1) ? 4 : 5; }
+inline int panel_tn_log(int tile) { return (tile & 2) ? 5 : 6; }
+inline bool panel_ok(int m, int n, int k, int b, tn_precision prec, int tile) {
+    return prec == TN_C64 && m >= 7 && n >= panel_tn_log(tile) && k >= panel_kc_log(tile) &&
+           (m - 7) + (n - panel_tn_log(tile)) + b < 40;
+}
+
 // Choose the kernel class and tile for C[b,m,n] = sum_k A[k,b,m] B[k,b,n]
 // (all sizes log2).  Dense steps go to MFMA tiles; steps whose output is tiny
 // but whose contracted dimension is long are split along K; everything else
@@ -46,6 +56,13 @@ inline void choose_kernel(int m, int n, int k, int b, tn_precision prec, int& ke
         kernel = 4;
         return;
     }
+    // dense complex64 steps: panel kernel, widest N tile that fits
+    for (int t : {0, 2})
+        if (panel_ok(m, n, k, b, prec, t) && k >= 6) {
+            kernel = 5;
+            tile = t;
+            return;
+        }
     if (mfma_capable(prec) && m >= 6 && n >= 3 && k >= 2) {
         int best = -1;
         for (int t = 0; t < kNumMfmaTiles; ++t) {

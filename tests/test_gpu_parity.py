@@ -245,13 +245,14 @@ def test_c3_random_circuit_slice_vs_oracle(branch_merge):
     """One slice of the bench workload against the oracle's complex128
     contraction (the plan's tree is only the oracle's schedule; results do not
     depend on the order).  Both trees run steps on the skinny MFMA kernel
-    (N of 16 to 64, with and without batch legs); the unmerged one also on
-    the streaming kernel."""
+    (N of 16 to 64, with and without batch legs) and on the panel MFMA kernel
+    (dense steps, K in chunks); the unmerged one also on the streaming
+    kernel."""
     w = rqc.workload("c3_5x8_m16")
     p = _c3_plan(w, branch_merge=branch_merge)
     ex = p.export()
     kinds = {st["kernel"] for st in ex["steps"]}
-    assert 4 in kinds and (branch_merge or 3 in kinds)
+    assert 4 in kinds and 5 in kinds and (branch_merge or 3 in kinds)
     sliced = [tuple(e) for e in ex["sliced"]]
     tree = list(zip(ex["lhs"], ex["rhs"]))
     net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
