@@ -96,10 +96,13 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
     if (d.d_max) {
         g.amax = d.d_max + p.nodes[st.a_node].slot;
         g.bmax = d.d_max + p.nodes[st.b_node].slot;
-        // the output's max is needed only when an MFMA step consumes it
+        // the output's max is needed only when a low-precision MFMA step
+        // (tiled or panel) consumes it
         const int parent = p.nodes[st.node].parent;
-        if (parent >= 0 && p.step_of_node[parent] >= 0 && p.steps[p.step_of_node[parent]].kernel == K_MFMA)
-            g.cmax = d.d_max + p.nodes[st.node].slot;
+        if (parent >= 0 && p.step_of_node[parent] >= 0) {
+            const int ck = p.steps[p.step_of_node[parent]].kernel;
+            if (ck == K_MFMA || ck == K_PANEL) g.cmax = d.d_max + p.nodes[st.node].slot;
+        }
     }
     const int mode = lp_mode(p.opts.prec);
     g.m_log = st.m_log;
@@ -167,7 +170,16 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
         if (name)
             *name = std::string("k_panel<") + (panel_kc_log(st.tile) == 5 ? "32," : "16,") +
                     (panel_tn_log(st.tile) == 6 ? "4>" : "2>");
-        hipError_t e = launch_panel(st.tile, g, s);
+        hipError_t e;
+        if (!panel_fp32(st.tile, p.opts.prec)) {
+            uint32_t* conv = (ws && st.conv_off != ~uint64_t(0))
+                                 ? reinterpret_cast<uint32_t*>((unsigned char*)ws + st.conv_off * (uint64_t)p.esize)
+                                 : nullptr;
+            if (name) *name = (conv ? "k_lp_convert_a+k_panel_lp<" : "k_panel_lp<") + name->substr(8);
+            e = launch_panel_lp(mode, st.tile & 3, g, conv, s);
+        } else {
+            e = launch_panel(st.tile & 3, g, s);
+        }
         if (e != hipSuccess) return std::string("panel launch: ") + hipGetErrorString(e);
         return "";
     }
@@ -476,7 +488,10 @@ std::vector<Candidate> candidates(const Step& st, tn_precision prec) {
             if (kMfmaTiles[t].tm_log <= st.m_log && kMfmaTiles[t].tn_log <= st.n_log) c.push_back({K_MFMA, t, 0});
     if (skinny_ok(st.m_log, st.n_log, st.k_log, st.b_log, prec)) c.push_back({K_SKINNY, 0, 0});
     for (int t = 0; t < kNumPanelTiles; ++t)
-        if (panel_ok(st.m_log, st.n_log, st.k_log, st.b_log, prec, t)) c.push_back({K_PANEL, t, 0});
+        if (panel_ok(st.m_log, st.n_log, st.k_log, st.b_log, prec, t)) {
+            c.push_back({K_PANEL, t, 0});
+            if (prec != TN_C64) c.push_back({K_PANEL, t | 4, 0});   // FP32 panel in a mixed form
+        }
     c.push_back({K_SMALL, 0, 0});
     if (st.k_log <= 4 && st.n_log <= 4 && st.m_log >= (prec == TN_C128 ? 8 : 9) &&
         st.b_log <= 16)

@@ -897,6 +897,207 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
     });
 }
 
+// Mixed-precision form of k_panel (v_mfma_f32_32x32x16_{f16,bf16}): lane
+// (r, h) supplies eight halves = four packed (re, im) words of complex k
+// 4 h .. 4 h + 3 of an 8-k step, for row r; B' words are staged in LDS k-fastest
+// (rows of real columns: (re, -im) for column 2n, (im, re) for 2n+1).  Split
+// mode runs hi*hi, hi*lo and lo*hi; the result is (acc + 2^-11 accx) * 2^(ea+eb).
+template <int KC, int NB, int MODE, bool PRE>
+__global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
+    constexpr int N = 16 * NB;
+    constexpr int NR = 2 * N;
+    constexpr bool SPLIT = MODE == LP_SPLIT_FP16;
+    constexpr int PL = SPLIT ? 2 : 1;
+    constexpr int RS = KC + 4;
+    constexpr int CS = 17;
+    constexpr int PBN = KC * N / 256;
+    constexpr int NS = KC / 8;               // MFMA steps (8 complex k) per chunk
+    __shared__ __attribute__((aligned(16))) uint32_t Bw[PL][NR * RS];
+    __shared__ __attribute__((aligned(16))) float2 Cs[128 * CS];
+    const TileIndex ti = tile_index(g);
+    const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
+    const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
+                      (ti.beta << g.m_log) + ti.m0;
+    const float2* B = reinterpret_cast<const float2*>(g.B) + slice_offset(g.d_slice, g.sb_n, g.sb_bit, g.sb_pos) +
+                      (ti.beta << g.n_log) + ti.n0;
+    const int ea = scale_exp(g.amax), eb = scale_exp(g.bmax);
+    const float sa = ldexpf(1.f, -ea), sb = ldexpf(1.f, -eb);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int r = lane & 31, h = lane >> 5;
+    const uint64_t K = 1ull << g.k_log;
+    // A: NS steps of 8 complex k per chunk; lane (r, h) holds complex k
+    // 4 h .. 4 h + 3 of each step for row r.  Without PRE they are loaded as
+    // complex64 and split here; with PRE they arrive split, as 16-byte groups
+    // of four k per row (planes g.A / g.a_lo, layout [K/4][batch, M][4]).
+    float2 av[PRE ? 1 : NS][4], an[PRE ? 1 : NS][4], bb[PBN];
+    uint4 ph[PRE ? NS : 1][PL], pn[PRE ? NS : 1][PL];
+    const uint64_t rowA = (ti.beta << g.m_log) + ti.m0 + w * 32 + r;
+    auto load_a = [&](float2 (&dst)[PRE ? 1 : NS][4], uint4 (&pdst)[PRE ? NS : 1][PL], uint64_t k0) {
+        if constexpr (PRE) {
+            const uint4* hp = reinterpret_cast<const uint4*>(g.A);
+            const uint4* lp = reinterpret_cast<const uint4*>(g.a_lo);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const uint64_t q = ((k0 >> 2) + 2 * s + h) * sAk + rowA;
+                pdst[s][0] = hp[q];
+                if constexpr (SPLIT) pdst[s][PL - 1] = lp[q];
+            }
+        } else {
+            const float2* src = A + w * 32 + r + (k0 + 4 * h) * sAk;
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dst[s][i] = src[(uint64_t)(8 * s + i) * sAk];
+        }
+    };
+    auto load_b = [&](uint64_t k0) {
+#pragma unroll
+        for (int i = 0; i < PBN; ++i) {
+            const int e = tid + 256 * i;
+            bb[i] = B[(k0 + e / N) * sBk + (e % N)];
+        }
+    };
+    floatx16 acc[NB], accx[SPLIT ? NB : 1];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
+    if constexpr (SPLIT) {
+#pragma unroll
+        for (int nb = 0; nb < (SPLIT ? NB : 1); ++nb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) accx[nb][v] = 0.f;
+    }
+    load_a(av, ph, 0);
+    load_b(0);
+    for (uint64_t k0 = 0; k0 < K; k0 += KC) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PBN; ++i) {
+            const int e = tid + 256 * i, kk = e / N, nn = e % N;
+            uint32_t hi, lo;
+            split_pack<MODE>(bb[i], sb, hi, lo);
+            Bw[0][(2 * nn) * RS + kk] = bexp(hi, 0);
+            Bw[0][(2 * nn + 1) * RS + kk] = bexp(hi, 1);
+            if constexpr (SPLIT) {
+                Bw[PL - 1][(2 * nn) * RS + kk] = bexp(lo, 0);
+                Bw[PL - 1][(2 * nn + 1) * RS + kk] = bexp(lo, 1);
+            }
+        }
+        __syncthreads();
+        if (k0 + KC < K) {
+            load_a(an, pn, k0 + KC);
+            load_b(k0 + KC);
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            uint4 ah, al;
+            if constexpr (PRE) {
+                ah = ph[s][0];
+                al = ph[s][PL - 1];
+            } else {
+                uint32_t hw[4], lw[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) split_pack<MODE>(av[s][i], sa, hw[i], lw[i]);
+                ah = uint4{hw[0], hw[1], hw[2], hw[3]};
+                al = uint4{lw[0], lw[1], lw[2], lw[3]};
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int o = (nb * 32 + r) * RS + 8 * s + 4 * h;
+                const uint4 bh = *reinterpret_cast<const uint4*>(&Bw[0][o]);
+                if constexpr (MODE == LP_BF16) {
+                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah),
+                                                                      __builtin_bit_cast(bf16x8, bh), acc[nb], 0, 0, 0);
+                } else {
+                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, ah),
+                                                                     __builtin_bit_cast(half8, bh), acc[nb], 0, 0, 0);
+                    if constexpr (SPLIT) {
+                        const uint4 bl = *reinterpret_cast<const uint4*>(&Bw[PL - 1][o]);
+                        accx[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, ah),
+                                                                          __builtin_bit_cast(half8, bl), accx[nb], 0, 0, 0);
+                        accx[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, al),
+                                                                          __builtin_bit_cast(half8, bh), accx[nb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if constexpr (PRE) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int p = 0; p < PL; ++p) ph[s][p] = pn[s][p];
+        } else {
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) av[s][i] = an[s][i];
+        }
+    }
+    const float sc = ldexpf(1.f, ea + eb);
+    uint64_t off_lo = 0;
+    int src_lo = 0;
+    for (int i = 0; i < 8; ++i)
+        if ((tid >> i) & 1) {
+            off_lo |= 1ull << g.ep_pos[i];
+            const int sbt = g.ep_src[i];
+            src_lo += sbt < 32 ? CS << sbt : 1 << (sbt - 32);
+        }
+    float mx = 0.f;
+    const uint64_t cbase = deposit(ti.m0, g.cpm, 7, g.m_log) + deposit(ti.beta, g.cpb, 0, g.b_log);
+    float* cs = reinterpret_cast<float*>(Cs);
+    float2* C = reinterpret_cast<float2*>(g.C);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            float x = acc[nb][v];
+            if constexpr (SPLIT) x = fmaf(accx[nb][v], 1.f / 2048.f, x);
+            x *= sc;
+            const int row = w * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+            cs[row * (2 * CS) + r] = x;
+            mx = fmaxf(mx, fabsf(x));
+        }
+        __syncthreads();
+        const uint64_t cb = cbase + deposit(ti.n0 + ((uint64_t)nb << 4), g.cpn, 4, g.n_log);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            uint64_t off_hi = 0;
+            int src_hi = 0;
+            for (int i = 8; i < g.ep_n; ++i)
+                if ((j >> (i - 8)) & 1) {
+                    off_hi |= 1ull << g.ep_pos[i];
+                    const int sbt = g.ep_src[i];
+                    src_hi += sbt < 32 ? CS << sbt : 1 << (sbt - 32);
+                }
+            C[cb + (off_lo | off_hi)] = Cs[src_lo + src_hi];
+        }
+    }
+    if (g.cmax) tile_max_atomic(mx, g.cmax);
+}
+
+
+// Split a complex64 A operand ([K | batch | M], scaled by 2^-e from the
+// producer's max) into word planes laid out [K/4][batch, M][4]: the four k of
+// one row that a lane of k_panel_lp needs are one 16-byte load.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_lp_convert_a(GemmArgs g, uint32_t* hi, uint32_t* lo) {
+    const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos);
+    const uint64_t rows = 1ull << (g.m_log + g.b_log);
+    const uint64_t n = rows << (g.k_log - 2);
+    const float sc = ldexpf(1.f, -scale_exp(g.amax));
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += stride) {
+        const uint64_t q = t / rows, row = t % rows;
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) split_pack<MODE>(A[(4 * q + i) * rows + row], sc, h[i], l[i]);
+        reinterpret_cast<uint4*>(hi)[t] = uint4{h[0], h[1], h[2], h[3]};
+        if constexpr (MODE == LP_SPLIT_FP16) reinterpret_cast<uint4*>(lo)[t] = uint4{l[0], l[1], l[2], l[3]};
+    }
+}
+
 __global__ void __launch_bounds__(256) k_fill(float* p, uint64_t n) {
     const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = 0.f;
@@ -1138,6 +1339,44 @@ static hipError_t launch_lp(int tile, const GemmArgs& g, dim3 grid, hipStream_t 
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int MODE, bool PRE>
+static hipError_t launch_panel_lp_t(int tile, const GemmArgs& g, dim3 grid, hipStream_t s) {
+    switch (tile) {
+        case 0: hipLaunchKernelGGL((k_panel_lp<32, 4, MODE, PRE>), grid, dim3(256), 0, s, g); break;
+        case 1: hipLaunchKernelGGL((k_panel_lp<16, 4, MODE, PRE>), grid, dim3(256), 0, s, g); break;
+        case 2: hipLaunchKernelGGL((k_panel_lp<32, 2, MODE, PRE>), grid, dim3(256), 0, s, g); break;
+        default: hipLaunchKernelGGL((k_panel_lp<16, 2, MODE, PRE>), grid, dim3(256), 0, s, g); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_panel_lp(int mode, int tile, const GemmArgs& g, uint32_t* conv, hipStream_t s) {
+    const int kc_log = (tile & 1) ? 4 : 5, nb_log = (tile & 2) ? 1 : 2;
+    if (tile < 0 || tile > 3 || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) || g.k_log < kc_log ||
+        g.ep_n != 11 || g.split_log != 0 || (mode != LP_SPLIT_FP16 && mode != LP_BF16))
+        return hipErrorInvalidValue;
+    const dim3 grid = grid_for(tile_blocks(g));
+    if (!conv) {
+        if (mode == LP_SPLIT_FP16) return launch_panel_lp_t<LP_SPLIT_FP16, false>(tile, g, grid, s);
+        return launch_panel_lp_t<LP_BF16, false>(tile, g, grid, s);
+    }
+    // one pass over A into word planes, then the GEMM on the planes
+    const uint64_t na = 1ull << (g.m_log + g.b_log + g.k_log);
+    uint32_t* hi = conv;
+    uint32_t* lo = conv + na;
+    const dim3 cgrid((unsigned)std::min<uint64_t>(((na >> 2) + 255) / 256, 16384));
+    if (mode == LP_SPLIT_FP16) hipLaunchKernelGGL(k_lp_convert_a<LP_SPLIT_FP16>, cgrid, dim3(256), 0, s, g, hi, lo);
+    else hipLaunchKernelGGL(k_lp_convert_a<LP_BF16>, cgrid, dim3(256), 0, s, g, hi, lo);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    GemmArgs h = g;
+    h.A = hi;
+    h.a_lo = lo;
+    h.sa_n = 0;   // the planes are already slice-selected
+    if (mode == LP_SPLIT_FP16) return launch_panel_lp_t<LP_SPLIT_FP16, true>(tile, h, grid, s);
+    return launch_panel_lp_t<LP_BF16, true>(tile, h, grid, s);
 }
 
 hipError_t launch_fill(float* p, uint64_t n, hipStream_t s) {

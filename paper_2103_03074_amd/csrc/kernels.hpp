@@ -25,6 +25,7 @@ struct GemmArgs {
     uint8_t ep_pos[16];     // address bit of the i-th lowest tile bit of C
     uint8_t ep_src[16];     // logical source: < 32 -> m bit, >= 32 -> n bit (src - 32)
     uint8_t cpm[kMaxBits], cpn[kMaxBits], cpb[kMaxBits];
+    const uint32_t* a_lo;   // k_panel_lp on pre-split A: lo word plane (A then points at the hi plane)
     const float* amax;      // max |re|,|im| of A and B (low-precision MFMA scaling), or null
     const float* bmax;
     float* cmax;            // producer epilogue: atomic max of |re|,|im| of C, or null
@@ -51,6 +52,9 @@ hipError_t launch_valu(int storage, const GemmArgs& g, int R, hipStream_t s);
 hipError_t launch_stream(int storage, const GemmArgs& g, hipStream_t s);
 hipError_t launch_skinny(const GemmArgs& g, hipStream_t s);   // complex64 storage, FP32 MFMA
 hipError_t launch_panel(int tile, const GemmArgs& g, hipStream_t s);   // complex64, FP32 MFMA
+// Mixed-precision panel (mode LP_SPLIT_FP16 or LP_BF16).  conv: scratch of
+// 2 * 2^(m+b+k) words for the split A planes, or null to split A in the GEMM.
+hipError_t launch_panel_lp(int mode, int tile, const GemmArgs& g, uint32_t* conv, hipStream_t s);
 hipError_t launch_splitk_reduce(int storage, const GemmArgs& g, hipStream_t s);
 hipError_t launch_mfma(int mode, int tile, const GemmArgs& g, hipStream_t s);   // mode -1: FP32, else LpMode
 hipError_t launch_fill(float* p, uint64_t n, hipStream_t s);

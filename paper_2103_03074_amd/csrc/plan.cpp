@@ -610,6 +610,15 @@ static std::string finalize(Plan& p) {
             st.scratch_off = ws.alloc(scr_elems);
             ws.release(st.scratch_off, scr_elems);
         }
+        bool panel_any = false;
+        for (int t = 0; t < kNumPanelTiles; ++t)
+            panel_any |= panel_ok(st.m_log, st.n_log, st.k_log, st.b_log, p.opts.prec, t);
+        if (lp_prec(p.opts.prec) && panel_any) {
+            // hi and lo word planes of A: 8 bytes per element, one storage element each
+            const uint64_t conv = uint64_t(1) << (st.m_log + st.k_log + st.b_log);
+            st.conv_off = ws.alloc(conv);
+            ws.release(st.conv_off, conv);
+        }
         for (int o : {st.a_node, st.b_node})
             if (p.nodes[o].home == HOME_WS) ws.release(p.nodes[o].off, uint64_t(1) << p.nodes[o].legs.size());
     }

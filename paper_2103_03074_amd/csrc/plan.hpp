@@ -104,6 +104,7 @@ struct Step {
     double bytes;             // algorithmic bytes at the storage width
     uint64_t c_off;           // offset of C in its arena (workspace or plan memory)
     uint64_t scratch_off;     // split-K partials (workspace)
+    uint64_t conv_off = ~uint64_t(0);   // split A planes of a mixed-precision panel step, or ~0
 };
 
 // Where a node's tensor lives when it is read.

@@ -24,6 +24,7 @@ constexpr MfmaTile kMfmaTiles[] = {
 constexpr int kNumMfmaTiles = sizeof(kMfmaTiles) / sizeof(kMfmaTiles[0]);
 
 inline bool mfma_capable(tn_precision p) { return p != TN_C128; }
+inline bool lp_prec(tn_precision p) { return p == TN_SPLIT_FP16 || p == TN_BF16; }
 
 // Skinny MFMA kernel: N = 16..64 complex columns, K = 2..64, B of at most 4096
 // complex elements (held in LDS), 128-row tiles, complex64 storage.
@@ -31,13 +32,17 @@ inline bool skinny_ok(int m, int n, int k, int b, tn_precision prec) {
     return mfma_capable(prec) && n >= 4 && n <= 6 && k >= 1 && k <= 6 && k + n <= 12 && m >= 7 && b <= 16;
 }
 
-// Panel MFMA kernel (complex64, FP32): 128 rows x 16 NB columns per block, K
-// in chunks of KC.  Tile id: bit 0 -> KC = 16 (else 32), bit 1 -> NB = 2 (else 4).
+// Panel MFMA kernel: 128 rows x 16 NB columns per block, K in chunks of KC;
+// FP32 for complex64, FP16/BF16 MFMA for the mixed forms (complex64
+// storage).  Tile id: bit 0 -> KC = 16 (else 32), bit 1 -> NB = 2 (else 4),
+// bit 2 -> FP32 MFMA even in a mixed form (the autotuner may pick it where
+// the low-precision GEMM is not faster).
 constexpr int kNumPanelTiles = 4;
 inline int panel_kc_log(int tile) { return (tile & 1) ? 4 : 5; }
 inline int panel_tn_log(int tile) { return (tile & 2) ? 5 : 6; }
+inline bool panel_fp32(int tile, tn_precision prec) { return prec == TN_C64 || (tile & 4); }
 inline bool panel_ok(int m, int n, int k, int b, tn_precision prec, int tile) {
-    return prec == TN_C64 && m >= 7 && n >= panel_tn_log(tile) && k >= panel_kc_log(tile) &&
+    return mfma_capable(prec) && m >= 7 && n >= panel_tn_log(tile) && k >= panel_kc_log(tile) &&
            (m - 7) + (n - panel_tn_log(tile)) + b < 40;
 }
 

@@ -309,9 +309,12 @@ def test_c2_mixed_precision_vs_statevector(c2_state, prec):
 
 @pytest.mark.parametrize("prec", ["split_fp16", "bf16"])
 def test_c3_mixed_precision_slice_vs_oracle(prec):
+    """Dense steps on the mixed panel kernel (A split once into FP16/BF16
+    word planes), big-times-small steps on the FP32 skinny kernel."""
     w = rqc.workload("c3_5x8_m16")
     p = _c3_plan(w, prec=prec)
     ex = p.export()
+    assert 5 in {st["kernel"] for st in ex["steps"]}
     sliced = [tuple(e) for e in ex["sliced"]]
     tree = list(zip(ex["lhs"], ex["rhs"]))
     net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
