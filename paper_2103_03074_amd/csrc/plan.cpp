@@ -358,7 +358,7 @@ static void choose_batch(const Network& net, const Tree& tree, const TreeLegs& t
     const uint64_t cap = opts.max_workspace_bytes > 0 ? (uint64_t)opts.max_workspace_bytes : (uint64_t(32) << 30);
     const int want = opts.batch_log2;
     SliceCost sc = slice_cost_tl(tl, tree, in_s);
-    const int size_cap = std::max(sc.max_log2, 28);
+    const int size_cap = std::max(sc.max_log2, 30);   // 2^30 complex64 = 8 GiB per tensor of a launch group
     batch.clear();
     if (!fixed_slicing) {
         std::vector<int> chosen;

@@ -64,10 +64,12 @@ static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, in
         const int m = a_bits - k, n = b_bits - k;
         const bool dense = std::max(m, n) >= 6 && std::min(m, n) >= 3 && k >= 2;
         const double flops = 8.0 * std::exp2((double)u_bits);
-        const double rate = dense ? 100e12 : 25e12;     // sustained FP32 MFMA vs VALU complex FMA
+        // rates measured on MI355X: complex64 MFMA steps ~110 TFLOP/s, VALU
+        // steps ~25 TFLOP/s, streaming steps ~4 TB/s
+        const double rate = dense ? 110e12 : 25e12;
         const double bytes = g_esize * (std::exp2((double)a_bits) + std::exp2((double)b_bits) +
                                         std::exp2((double)out_bits));
-        c = std::max(flops / rate, bytes / 6e12) * 1e12 + 2.0e6;   // + per-launch overhead (~2 us)
+        c = std::max(flops / rate, bytes / 4e12) * 1e12 + 2.0e6;   // + per-launch overhead (~2 us)
     }
     if (out_bits > target) c *= std::exp2(4.0 * (out_bits - target) + 20.0);
     return c;
