@@ -472,6 +472,7 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
 // ------------------------------------------------------- skinny MFMA
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatv2 __attribute__((ext_vector_type(2)));
 
 // Big-times-small steps with N = 16..64 and K = 2..64 complex (the steps that
 // dominate once small branches are merged, appendix B): HBM-bound, so A is
@@ -524,7 +525,10 @@ __global__ void __launch_bounds__(256) k_skinny(GemmArgs g) {
     auto load = [&](float2* dst, uint64_t tt) {
         const float2* src = A + tt * 128 + w * 32 + r + (uint64_t)h * sAk;
 #pragma unroll
-        for (int p = 0; p < KP; ++p) dst[p] = src[(uint64_t)(2 * p) * sAk];
+        for (int p = 0; p < KP; ++p) {   // A is read once: non-temporal (streaming) loads
+            const floatv2 t = __builtin_nontemporal_load(reinterpret_cast<const floatv2*>(src + (uint64_t)(2 * p) * sAk));
+            dst[p] = float2{t.x, t.y};
+        }
     };
     if (t < tiles) load(a, t);
     float mx = 0.f;
@@ -625,16 +629,18 @@ __global__ void __launch_bounds__(256) k_panel(GemmArgs g) {
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
-    load_a(a, 0);
+    // B before A: the wait for the B chunk (in-order load counter) then
+    // leaves the A loads of the same chunk in flight
     load_b(0);
+    load_a(a, 0);
     for (uint64_t k0 = 0; k0 < K; k0 += KC) {
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < PBN; ++i) Bs[tid + 256 * i] = bb[i];
         __syncthreads();
         if (k0 + KC < K) {
-            load_a(an, k0 + KC);
             load_b(k0 + KC);
+            load_a(an, k0 + KC);
         }
 #pragma unroll
         for (int p = 0; p < KP; ++p) {
@@ -968,8 +974,8 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) accx[nb][v] = 0.f;
     }
+    load_b(0);   // B first: see k_panel
     load_a(av, ph, 0);
-    load_b(0);
     for (uint64_t k0 = 0; k0 < K; k0 += KC) {
         __syncthreads();
 #pragma unroll
@@ -986,8 +992,8 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
         }
         __syncthreads();
         if (k0 + KC < K) {
-            load_a(an, pn, k0 + KC);
             load_b(k0 + KC);
+            load_a(an, pn, k0 + KC);
         }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {

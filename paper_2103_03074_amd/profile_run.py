@@ -26,6 +26,9 @@ def main():
     ap.add_argument("--restarts", type=int, default=16)
     ap.add_argument("--branch-merge", type=int, default=1)
     ap.add_argument("--tune-cache", default="", help="autotuner cache (read, and extended)")
+    ap.add_argument("--events", action="store_true",
+                    help="also time every step with the library's HIP events (as bench.py does) and print "
+                         "the mean per launch of each device function")
     args = ap.parse_args()
     import torch
     import rqc
@@ -40,7 +43,21 @@ def main():
     p.autotune(ws, acc, args.tune_cache or None, reps=5)
     acc.zero_()
     per = 2 ** s["batch_log2"]
+    if args.events:
+        p.set_profiling(True)
     p.contract_slices(ws, acc, 0, per * args.groups)
+    if args.events:
+        torch.cuda.synchronize()
+        agg = {}
+        for st in p.step_profile():
+            a = agg.setdefault(st["kernel_name"], [0.0, 0])
+            a[0] += st["total_ms"]
+            a[1] += st["launches"]
+        p.set_profiling(False)
+        for name, (ms, n) in sorted(agg.items(), key=lambda kv: -kv[1][0]):
+            if n:
+                print(f"profile_run events: {name} launches {n} mean_us {1e3 * ms / n:.2f}", file=sys.stderr,
+                      flush=True)
     n = args.copy_mib << 18                      # float32 elements
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
