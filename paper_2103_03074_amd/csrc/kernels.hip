@@ -1386,6 +1386,7 @@ hipError_t launch_panel_lp(int mode, int tile, const GemmArgs& g, uint32_t* conv
 }
 
 hipError_t launch_fill(float* p, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;   // nothing to clear (e.g. every tensor slice-invariant)
     hipLaunchKernelGGL(k_fill, grid_for((n + 255) / 256), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }

@@ -307,6 +307,23 @@ def test_c2_mixed_precision_vs_statevector(c2_state, prec):
     assert err < MIXED_TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["c64", "split_fp16", "bf16"])
+def test_c2_unsliced_panel_steps_in_the_invariant_part(c2_state, prec):
+    """Without slicing every step is slice-invariant and runs once, outside
+    the workspace: the mixed panel kernel then splits A inside the GEMM
+    (no separate split pass)."""
+    w, psi = c2_state
+    p = _plan(w, n_slice_edges=0, max_log2_size=30, restarts=4, prec=prec, branch_merge=1)
+    ex = p.export()
+    assert any(st["kernel"] == 5 and st["invariant"] for st in ex["steps"])
+    _say("c2 unsliced", prec)
+    got = _run(p)
+    ref = sv.amplitudes_from_state(psi, 25, w["open_q"], w["fixed_q"], w["bits"])
+    err = _rel(got, ref)
+    _say("c2 unsliced", prec, "norm-rel error", err)
+    assert err < (C64_TOL if prec == "c64" else MIXED_TOL[prec])
+
+
 @pytest.mark.parametrize("prec", ["split_fp16", "bf16"])
 def test_c3_mixed_precision_slice_vs_oracle(prec):
     """Dense steps on the mixed panel kernel (A split once into FP16/BF16
