@@ -100,8 +100,10 @@ typedef struct {
     int32_t batch_log2;      /* slices contracted together per launch sequence
                                 (log2); -1 = chosen by the planner */
     int32_t branch_merge;    /* 1 = merge small branches before large steps */
-    int32_t bighead;         /* 1 = head/tail split with the head summed over slices
-                                and the tail applied once; 0 = single tree */
+    int32_t bighead;         /* must be 0: the head/tail split comes from the contraction
+                                order (the open legs join at the last steps); a head summed
+                                over slices before one tail product (1) returns
+                                TN_EUNSUPPORTED */
     int32_t restarts;        /* randomised greedy trees tried (>= 1) */
     int32_t cost_model;      /* 0 = FLOP/byte roofline model, 1 = learned MLP */
     uint64_t seed;
@@ -114,13 +116,13 @@ typedef struct {
     int32_t n_sliced;             /* sliced edges */
     int32_t batch_log2;           /* slices per launch sequence (log2) */
     int32_t n_open, n_leaves, n_steps;
-    int32_t n_c;                  /* cut legs between head and tail (bighead), else 0 */
+    int32_t n_c;                  /* cut legs of a separate head/tail split: always 0 */
     int32_t max_log2_size;        /* largest intermediate of one slice (log2 elements) */
     int32_t acc_log2;             /* accumulator length = 2^acc_log2 complex128 */
     double cmacs_per_slice;       /* complex multiply-adds per slice, executed tree */
     double cmacs_per_slice_unmerged; /* same before branch merging */
     double cmacs_invariant;       /* slice-invariant work done once per plan */
-    double cmacs_tail;            /* tail / amplitude work done once per run */
+    double cmacs_tail;            /* work of a separate tail: always 0 (the tail is part of the tree) */
     double bytes_per_slice;       /* algorithmic HBM bytes per slice (operands + results) */
     double cmacs_per_batch;       /* complex multiply-adds per launch sequence */
     double bytes_per_batch;
@@ -144,8 +146,9 @@ typedef struct {
 
 /* Build a plan (host only; no device work).  Section "The algorithm" and
  * appendix A: contraction order (randomised greedy, or the caller's tree),
- * slicing to the memory target, slice-invariant subtrees hoisted, big-head
- * split, branch merging, per-step layouts.
+ * slicing to the memory target, slice-invariant subtrees hoisted, branch
+ * merging, per-step layouts; the big-head split is the order's first cut
+ * (open legs on one side).
  *   c              circuit (copied)
  *   open_q/fixed_q disjoint, together every qubit exactly once
  *   fixed_bits     s1, one byte (0/1) per fixed qubit, in fixed_q order

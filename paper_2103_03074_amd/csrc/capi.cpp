@@ -59,6 +59,10 @@ tn_status tn_plan(const tn_circuit* c, const int32_t* open_q, int32_t n_open, co
         std::vector<int> o(open_q, open_q + n_open), f(fixed_q, fixed_q + n_fixed);
         std::vector<uint8_t> b(fixed_bits, fixed_bits + n_fixed);
         tn_plan_opts op = opts ? *opts : tn::default_opts();
+        if (op.bighead != 0)
+            return fail(TN_EUNSUPPORTED,
+                        "bighead = 1 (a head summed over slices before one tail product) is not implemented; "
+                        "the head/tail split comes from the contraction order, with the open legs entering last");
         tn::CostModel cm;
         const tn::CostModel* cmp = nullptr;
         if (op.cost_model == 1 && op.model) {

@@ -108,6 +108,13 @@ def test_planner_rejects_bad_input(case):
     assert ei.value.status == -1
 
 
+def test_unimplemented_option_is_refused():
+    w = rqc.workload("c1_tiny_3x4_m8")
+    with pytest.raises(tn.TnError) as ei:
+        tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], bighead=1)
+    assert ei.value.status == -5 and "bighead" in str(ei.value)
+
+
 def test_planner_degenerate_networks():
     # one qubit pair, one gate; and a qubit with no two-qubit gate
     c = rqc.random_circuit(rqc.rect_layout(1, 3), 1, seed=1)
