@@ -30,7 +30,10 @@ def precision_study(n_samples=256, precs=("c128", "c64", "split_fp16", "bf16"), 
     import rqc
     from . import tn, runtime
     w = rqc.workload("c4_diag53_m20")
-    base = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], restarts=restarts, seed=0, branch_merge=1)
+    # sampled slices are scattered over the 2^k ids: one slice per launch
+    # group, so no sampled slice pays for the rest of a group
+    base = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], restarts=restarts, seed=0, branch_merge=1,
+                   batch_log2=0)
     ex = base.export()
     tree = list(zip(ex["lhs"], ex["rhs"]))
     sliced = [tuple(e) for e in ex["sliced"]]
@@ -41,7 +44,8 @@ def precision_study(n_samples=256, precs=("c128", "c64", "split_fp16", "bf16"), 
            "n_samples": len(ids), "weight": weight, "forms": {}}
     amps = {}
     for prec in precs:
-        p = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], tree=tree, sliced=sliced, prec=prec)
+        p = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], tree=tree, sliced=sliced, prec=prec,
+                    batch_log2=0)
         s = p.stats()
         ws = runtime.workspace(p)
         acc = runtime.accumulator(p)
