@@ -100,10 +100,15 @@ typedef struct {
     int32_t batch_log2;      /* slices contracted together per launch sequence
                                 (log2); -1 = chosen by the planner */
     int32_t branch_merge;    /* 1 = merge small branches before large steps */
-    int32_t bighead;         /* must be 0: the head/tail split comes from the contraction
-                                order (the open legs join at the last steps); a head summed
-                                over slices before one tail product (1) returns
-                                TN_EUNSUPPORTED */
+    int32_t bighead;         /* 1 = big-head split (section "Big-head simulation"): a tail
+                                holding every open leg is cut off with n_c <= 28 cut legs;
+                                all sliced edges lie in the head, whose result v_head[c] is
+                                what the slices sum into (the accumulator has 2^n_c
+                                entries).  tn_amplitudes contracts the tail network with
+                                v_head as one more leaf, once, in complex128, giving
+                                A[s2] = sum_c T_tail[s2, c] v_head[c] without forming
+                                T_tail.  Needs tree = NULL and planner-chosen slicing
+                                (TN_EINVAL otherwise).  0 = one tree whose root gives A. */
     int32_t restarts;        /* randomised greedy trees tried (>= 1) */
     int32_t cost_model;      /* 0 = FLOP/byte roofline model, 1 = learned MLP */
     uint64_t seed;
@@ -116,18 +121,18 @@ typedef struct {
     int32_t n_sliced;             /* sliced edges */
     int32_t batch_log2;           /* slices per launch sequence (log2) */
     int32_t n_open, n_leaves, n_steps;
-    int32_t n_c;                  /* cut legs of a separate head/tail split: always 0 */
+    int32_t n_c;                  /* cut legs between head and tail (bighead), else 0 */
     int32_t max_log2_size;        /* largest intermediate of one slice (log2 elements) */
     int32_t acc_log2;             /* accumulator length = 2^acc_log2 complex128 */
     double cmacs_per_slice;       /* complex multiply-adds per slice, executed tree */
     double cmacs_per_slice_unmerged; /* same before branch merging */
     double cmacs_invariant;       /* slice-invariant work done once per plan */
-    double cmacs_tail;            /* work of a separate tail: always 0 (the tail is part of the tree) */
+    double cmacs_tail;            /* tail network with the v_head leaf, per tn_amplitudes call (bighead) */
     double bytes_per_slice;       /* algorithmic HBM bytes per slice (operands + results) */
     double cmacs_per_batch;       /* complex multiply-adds per launch sequence */
     double bytes_per_batch;
     uint64_t workspace_bytes;     /* minimum ws_bytes for tn_contract_slices */
-    uint64_t tail_workspace_bytes;/* minimum ws_bytes for tn_amplitudes */
+    uint64_t tail_workspace_bytes;/* minimum ws_bytes for tn_amplitudes (bighead; else 0) */
     int32_t n_dense_steps;        /* steps run on MFMA (tiled, skinny or panel) */
     int32_t n_small_steps;        /* steps run on the VALU kernels (tile, split-K, streaming) */
     int32_t cost_model_used;      /* 0 FLOP count, 1 learned model, 2 learned model asked but
@@ -147,8 +152,7 @@ typedef struct {
 /* Build a plan (host only; no device work).  Section "The algorithm" and
  * appendix A: contraction order (randomised greedy, or the caller's tree),
  * slicing to the memory target, slice-invariant subtrees hoisted, branch
- * merging, per-step layouts; the big-head split is the order's first cut
- * (open legs on one side).
+ * merging, per-step layouts; optionally the big-head split (opts->bighead).
  *   c              circuit (copied)
  *   open_q/fixed_q disjoint, together every qubit exactly once
  *   fixed_bits     s1, one byte (0/1) per fixed qubit, in fixed_q order
@@ -194,8 +198,11 @@ tn_status tn_contract_slice_list(tn_plan_t p, void* d_workspace, size_t ws_bytes
 /* Turn the accumulator into the 2^n_open amplitudes d_amps (complex128):
  * with the big-head split this contracts the tail with the summed head
  * vector (section "Big-head simulation", the final inner product
- * v_head . v_tail(s2)); without it the accumulator already holds A and is
- * copied.  d_workspace must hold stats.tail_workspace_bytes. */
+ * v_head . v_tail(s2)): the accumulator is copied to the host, placed as the
+ * tail's last leaf and the tail contracted on hip_stream, which is
+ * synchronised (the tail's slice-free steps run at the first call only).
+ * Without the split the accumulator already holds A and is copied.
+ * d_workspace must hold stats.tail_workspace_bytes (TN_EINVAL otherwise). */
 tn_status tn_amplitudes(tn_plan_t p, const double* d_acc, double* d_amps,
                         void* d_workspace, size_t ws_bytes, void* hip_stream);
 

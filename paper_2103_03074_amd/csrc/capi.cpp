@@ -15,6 +15,8 @@
 struct tn_plan_s {
     tn::Plan plan;
     tn::DeviceState dev;
+    // big-head split: the tail plan (tail network + a leaf for v_head)
+    tn_plan_s* tail = nullptr;
 };
 
 struct tn_mlp_s {
@@ -59,10 +61,6 @@ tn_status tn_plan(const tn_circuit* c, const int32_t* open_q, int32_t n_open, co
         std::vector<int> o(open_q, open_q + n_open), f(fixed_q, fixed_q + n_fixed);
         std::vector<uint8_t> b(fixed_bits, fixed_bits + n_fixed);
         tn_plan_opts op = opts ? *opts : tn::default_opts();
-        if (op.bighead != 0)
-            return fail(TN_EUNSUPPORTED,
-                        "bighead = 1 (a head summed over slices before one tail product) is not implemented; "
-                        "the head/tail split comes from the contraction order, with the open legs entering last");
         tn::CostModel cm;
         const tn::CostModel* cmp = nullptr;
         if (op.cost_model == 1 && op.model) {
@@ -216,10 +214,42 @@ tn_status tn_contract_slice_list(tn_plan_t p, void* d_workspace, size_t ws_bytes
 
 tn_status tn_amplitudes(tn_plan_t p, const double* d_acc, double* d_amps, void* d_workspace, size_t ws_bytes,
                         void* hip_stream) {
-    (void)d_workspace;
-    (void)ws_bytes;
     if (!p || !d_acc || !d_amps) return fail(TN_EINVAL, "NULL argument");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    if (p->plan.tail) {
+        // big-head: v_head (the accumulator, summed over slices) becomes the
+        // last leaf of the tail network, which is contracted once in
+        // complex128 into A[s2] = sum_c T_tail[s2, c] v_head[c]
+        const int n_c = p->plan.stats.n_c, n_open = p->plan.stats.n_open;
+        if (!d_workspace || ws_bytes < p->plan.stats.tail_workspace_bytes)
+            return fail(TN_EINVAL, "workspace smaller than stats.tail_workspace_bytes");
+        try {
+            if (!p->tail) {
+                p->tail = new tn_plan_s;
+                p->tail->plan = *p->plan.tail;
+            }
+            tn::Plan& tp = p->tail->plan;
+            std::string err = tn::prepare(tp, p->tail->dev, s);   // tail-only steps, once
+            if (!err.empty()) return fail(TN_EDEVICE, err);
+            std::vector<double> h(2ull << n_c);
+            hipError_t e = hipMemcpyAsync(h.data(), d_acc, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return fail(TN_EDEVICE, std::string("v_head download: ") + hipGetErrorString(e));
+            std::vector<tn::cd> v(size_t(1) << n_c);
+            for (size_t i = 0; i < v.size(); ++i) v[i] = tn::cd(h[2 * i], h[2 * i + 1]);
+            err = tn::upload_leaf(tp, p->tail->dev, tp.tree.n_leaves - 1, v, s);
+            if (!err.empty()) return fail(TN_EDEVICE, err);
+            if ((e = hipMemsetAsync(d_amps, 0, sizeof(double) * (2ull << n_open), s)) != hipSuccess)
+                return fail(TN_EDEVICE, std::string("amplitudes: ") + hipGetErrorString(e));
+            tn::Group g;
+            g.slice_base = 0;
+            g.beta0 = 0;
+            g.beta1 = 1;
+            return from_err(tn::run_groups(tp, p->tail->dev, d_workspace, d_amps, {g}, s));
+        } catch (const std::bad_alloc&) {
+            return fail(TN_ENOMEM, "host allocation failed");
+        }
+    }
     const uint64_t n = 2ull << p->plan.root_log2;
     hipError_t e = tn::launch_copy_acc(d_acc, d_amps, n, s);
     if (e != hipSuccess) return fail(TN_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
@@ -473,6 +503,7 @@ void tn_mlp_destroy(tn_mlp_t m) {
 
 void tn_plan_destroy(tn_plan_t p) {
     if (!p) return;
+    if (p->tail) tn_plan_destroy(p->tail);
     if (p->dev.prepared || p->dev.plan_mem) {
         int cur = 0;
         if (hipGetDevice(&cur) == hipSuccess && p->dev.device >= 0 && cur != p->dev.device) {

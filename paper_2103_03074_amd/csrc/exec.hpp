@@ -45,6 +45,8 @@ struct Group {
 };
 
 std::string prepare(Plan& p, DeviceState& d, hipStream_t s);
+// Replace the data of a leaf (natural order of its legs) in prepared plan memory.
+std::string upload_leaf(Plan& p, DeviceState& d, int leaf, const std::vector<cd>& data, hipStream_t s);
 std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std::vector<Group>& groups,
                        hipStream_t s);
 void release(DeviceState& d);

@@ -454,6 +454,7 @@ static std::string finalize(Plan& p) {
             p.nodes[i].dep |= (bool)in_s[e];
             if (!in_s[e] || in_b[e]) p.nodes[i].legs.push_back(e);
         }
+        if (i < (int)p.force_dep.size() && p.force_dep[i]) p.nodes[i].dep = true;
         p.nodes[i].home = HOME_LEAF;
     }
     for (size_t s = 0; s < t.lhs.size(); ++s) {
@@ -673,35 +674,14 @@ static void fill_stats(Plan& p) {
     s.n_c = 0;
 }
 
-std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
-                      const std::vector<int>& fixed_q, const std::vector<uint8_t>& bits,
-                      const tn_tree* tree, const tn_edge* sliced, int n_sliced,
-                      const tn_plan_opts& opts, Plan& out, const CostModel* cm) {
-    out = Plan();
-    out.opts = opts;
-    if (opts.prec < TN_C64 || opts.prec > TN_BF16) return "unknown precision";
-    if (opts.max_log2_size < 1 || opts.max_log2_size > 40) return "max_log2_size out of range";
-    out.esize = storage_bytes(opts.prec);
-    std::string err = build_network(c, open_q, fixed_q, bits, out.net);
-    if (!err.empty()) return err;
+// Planning pipeline on a built network (out.net, out.opts and out.esize set).
+static std::string plan_network(Plan& out, const tn_tree* tree, const std::vector<int>& user_sliced,
+                                bool fixed_slicing, const CostModel* cm, const Tree* extra = nullptr) {
+    const tn_plan_opts& opts = out.opts;
     const Network& net = out.net;
     const int E = (int)net.edge_name.size();
     const int L = (int)net.leaves.size();
-    std::vector<int> user_sliced;
-    if (sliced && n_sliced > 0) {
-        std::vector<char> seen(E, 0), is_open(E, 0);
-        for (int e : net.open_edges) is_open[e] = 1;
-        for (int i = 0; i < n_sliced; ++i) {
-            int e = net.find_edge(sliced[i].qubit, sliced[i].segment);
-            if (e < 0) return "sliced edge (" + std::to_string(sliced[i].qubit) + "," +
-                              std::to_string(sliced[i].segment) + ") is not an edge";
-            if (is_open[e]) return "an open leg cannot be sliced";
-            if (seen[e]) return "sliced edge repeated";
-            seen[e] = 1;
-            user_sliced.push_back(e);
-        }
-    }
-    const bool fixed_slicing = n_sliced >= 0;
+    std::string err;
     std::vector<Legs> leaf_legs(L);
     for (int i = 0; i < L; ++i) {
         leaf_legs[i] = net.leaves[i].legs;
@@ -743,6 +723,7 @@ std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
                 cands.push_back(greedy_tree(leaf_legs, opts.seed * 1000003ULL + r, alpha, temp));
             }
         }
+        if (extra && extra->n_leaves == L) cands.push_back(*extra);
     }
     if (L == 1) {
         cands.clear();
@@ -882,6 +863,262 @@ std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
     out.stats.n_candidates = n_cand;
     out.stats.cost_model_used = model_used;
     out.stats.predicted_ms = predicted;
+    return "";
+}
+
+// Big-head split (section "Big-head simulation of quantum circuits", Fig. 1):
+// the tail is a set of leaves holding every open leg, grown greedily from the
+// leaves with open legs (adjacent leaf of smallest cut change, plateaus
+// allowed, at most half the network; the smallest cut seen is kept);
+// n_c is bounded so that the head's accumulator stays within 2^28 entries.
+static std::vector<char> choose_tail(const Network& net, int max_log2) {
+    const int L = (int)net.leaves.size();
+    const int E = (int)net.edge_name.size();
+    std::vector<char> is_open(E, 0), in_t(L, 0);
+    for (int e : net.open_edges) is_open[e] = 1;
+    std::vector<std::vector<int>> ends(E);
+    for (int i = 0; i < L; ++i)
+        for (int e : net.leaves[i].legs) ends[e].push_back(i);
+    for (int i = 0; i < L; ++i)
+        for (int e : net.leaves[i].legs)
+            if (is_open[e]) in_t[i] = 1;
+    // change of the cut when leaf i joins the tail: its legs to tail leaves
+    // leave the cut, its legs to head leaves enter it
+    auto delta = [&](int i) {
+        int d = 0;
+        for (int e : net.leaves[i].legs) {
+            if (ends[e].size() != 2) continue;
+            const int j = ends[e][0] == i ? ends[e][1] : ends[e][0];
+            d += in_t[j] ? -1 : 1;
+        }
+        return d;
+    };
+    int cut = 0, n_t = 0;
+    for (int e = 0; e < E; ++e)
+        if (ends[e].size() == 2 && in_t[ends[e][0]] != in_t[ends[e][1]]) ++cut;
+    for (int i = 0; i < L; ++i) n_t += in_t[i];
+    const int n_open = (int)net.open_edges.size();
+    // grow by the adjacent leaf of smallest cut change (ties: lowest id),
+    // plateaus included, up to half the network; keep the smallest cut seen
+    std::vector<char> best_t = in_t;
+    int best_cut = cut;
+    while (2 * (n_t + 1) <= L) {
+        int pick = -1, pick_d = 0;
+        for (int i = 0; i < L; ++i) {
+            if (in_t[i]) continue;
+            bool adj = false;
+            for (int e : net.leaves[i].legs)
+                for (int j : ends[e]) adj |= (j != i && in_t[j]);
+            if (!adj) continue;
+            const int d = delta(i);
+            if (pick < 0 || d < pick_d) {
+                pick = i;
+                pick_d = d;
+            }
+        }
+        if (pick < 0 || pick_d > 0) break;
+        in_t[pick] = 1;
+        ++n_t;
+        cut += pick_d;
+        if (cut < best_cut) {
+            best_cut = cut;
+            best_t = in_t;
+        }
+    }
+    (void)n_open;
+    if (best_cut > max_log2) return {};
+    return best_t;
+}
+
+// A network over a subset of leaves with the given open edges (edge ids and
+// names are those of the full network).
+static Network sub_network(const Network& net, const std::vector<char>& keep, const std::vector<int>& open) {
+    Network s;
+    s.n_qubits = net.n_qubits;
+    s.edge_name = net.edge_name;
+    s.end0.assign(net.edge_name.size(), -1);
+    s.end1.assign(net.edge_name.size(), -1);
+    for (size_t i = 0; i < net.leaves.size(); ++i)
+        if (keep[i]) {
+            const int id = (int)s.leaves.size();
+            s.leaves.push_back(net.leaves[i]);
+            for (int e : net.leaves[i].legs) {
+                if (s.end0[e] < 0) s.end0[e] = id;
+                else s.end1[e] = id;
+            }
+        }
+    s.open_edges = open;
+    return s;
+}
+
+std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
+                      const std::vector<int>& fixed_q, const std::vector<uint8_t>& bits,
+                      const tn_tree* tree, const tn_edge* sliced, int n_sliced,
+                      const tn_plan_opts& opts, Plan& out, const CostModel* cm) {
+    out = Plan();
+    out.opts = opts;
+    if (opts.prec < TN_C64 || opts.prec > TN_BF16) return "unknown precision";
+    if (opts.max_log2_size < 1 || opts.max_log2_size > 40) return "max_log2_size out of range";
+    out.esize = storage_bytes(opts.prec);
+    Network full;
+    std::string err = build_network(c, open_q, fixed_q, bits, full);
+    if (!err.empty()) return err;
+    const int E = (int)full.edge_name.size();
+    std::vector<int> user_sliced;
+    if (sliced && n_sliced > 0) {
+        std::vector<char> seen(E, 0), is_open(E, 0);
+        for (int e : full.open_edges) is_open[e] = 1;
+        for (int i = 0; i < n_sliced; ++i) {
+            int e = full.find_edge(sliced[i].qubit, sliced[i].segment);
+            if (e < 0) return "sliced edge (" + std::to_string(sliced[i].qubit) + "," +
+                              std::to_string(sliced[i].segment) + ") is not an edge";
+            if (is_open[e]) return "an open leg cannot be sliced";
+            if (seen[e]) return "sliced edge repeated";
+            seen[e] = 1;
+            user_sliced.push_back(e);
+        }
+    }
+    if (!opts.bighead) {
+        out.net = std::move(full);
+        return plan_network(out, tree, user_sliced, n_sliced >= 0, cm);
+    }
+    // big-head: head over the leaves outside the tail, whose result
+    // v_head[c] (c = the cut legs) is summed over all slices; at the end the
+    // tail network plus one leaf holding v_head is contracted once, in
+    // complex128, straight into A[s2] = sum_c T_tail[s2, c] v_head[c]
+    if (tree || (sliced && n_sliced > 0)) return "bighead: the planner chooses the tree and the sliced edges";
+    // Tail candidates: (1) the leaves under the lowest node of the best
+    // full-network order that holds every open leg (the order is found
+    // first and the bottleneck read off it), when that node is not the
+    // root; (2) the greedy smallest-cut tail.  The cheaper split (head over
+    // all slices plus tail once) is kept.
+    Plan fullp;
+    fullp.opts = opts;
+    fullp.opts.bighead = 0;
+    fullp.esize = out.esize;
+    fullp.net = full;
+    err = plan_network(fullp, nullptr, {}, false, cm);
+    if (!err.empty()) return err;
+    std::vector<std::pair<std::vector<char>, Tree>> tails;   // tail leaves, induced head order
+    {
+        const Tree& ft = fullp.tree;
+        const int L = ft.n_leaves, N = ft.n_nodes();
+        std::vector<char> has_open(L, 0);
+        {
+            std::vector<char> is_open(E, 0);
+            for (int e : full.open_edges) is_open[e] = 1;
+            for (int i = 0; i < L; ++i)
+                for (int e : full.leaves[i].legs) has_open[i] |= is_open[e];
+        }
+        int total = 0;
+        for (int i = 0; i < L; ++i) total += has_open[i];
+        std::vector<int> cnt(N, 0);
+        for (int i = 0; i < L; ++i) cnt[i] = has_open[i];
+        for (int k = 0; k < (int)ft.lhs.size(); ++k) cnt[L + k] = cnt[ft.lhs[k]] + cnt[ft.rhs[k]];
+        int lca = -1;
+        for (int v = 0; v < N && total > 0; ++v)
+            if (cnt[v] == total) {
+                lca = v;
+                break;
+            }
+        if (lca >= 0 && lca != ft.root()) {
+            std::vector<char> under(N, 0), in_t(L, 0);
+            under[lca] = 1;
+            for (int k = (int)ft.lhs.size() - 1; k >= 0; --k)
+                if (under[L + k]) under[ft.lhs[k]] = under[ft.rhs[k]] = 1;
+            for (int i = 0; i < L; ++i) in_t[i] = under[i];
+            tails.push_back({in_t, Tree()});
+        }
+    }
+    {
+        std::vector<char> g = choose_tail(full, 28);
+        if (!g.empty()) tails.push_back({g, Tree()});
+    }
+    // each head also gets the full order restricted to its leaves as a candidate
+    for (auto& cand : tails) {
+        const Tree& ft = fullp.tree;
+        const int L = ft.n_leaves, N = ft.n_nodes();
+        std::vector<int> map(N, -1);
+        Tree& ht = cand.second;
+        ht = Tree();
+        for (int i = 0; i < L; ++i)
+            if (!cand.first[i]) map[i] = ht.n_leaves++;
+        for (int k = 0; k < (int)ft.lhs.size(); ++k) {
+            const int a = map[ft.lhs[k]], b = map[ft.rhs[k]];
+            if (a >= 0 && b >= 0) {
+                map[L + k] = ht.n_leaves + (int)ht.lhs.size();
+                ht.lhs.push_back(a);
+                ht.rhs.push_back(b);
+            } else {
+                map[L + k] = a >= 0 ? a : b;
+            }
+        }
+    }
+    if (tails.empty()) return "bighead: no tail with at most 28 cut legs found";
+    std::string last_err = "bighead: no tail with at most 28 cut legs found";
+    double best = -1;
+    for (auto& cand : tails) {
+        const std::vector<char>& in_t = cand.first;
+        std::vector<char> in_h(in_t.size());
+        for (size_t i = 0; i < in_t.size(); ++i) in_h[i] = !in_t[i];
+        std::vector<int> cut;
+        {
+            std::vector<int> cnt_t(E, 0), cnt_h(E, 0);
+            for (size_t i = 0; i < full.leaves.size(); ++i)
+                for (int e : full.leaves[i].legs) (in_t[i] ? cnt_t : cnt_h)[e]++;
+            for (int e = 0; e < E; ++e)
+                if (cnt_t[e] == 1 && cnt_h[e] == 1) cut.push_back(e);
+        }
+        const int n_c = (int)cut.size();
+        if (n_c > 28) continue;
+        Plan h;
+        h.opts = opts;
+        h.esize = out.esize;
+        h.net = sub_network(full, in_h, cut);   // accumulator index: cut[0] most significant
+        Network tail_net = sub_network(full, in_t, full.open_edges);
+        {
+            HostTensor v;   // address bit j <-> cut[n_c - 1 - j], as in the head's accumulator
+            for (int j = n_c - 1; j >= 0; --j) v.legs.push_back(cut[j]);
+            v.data.assign(size_t(1) << n_c, cd(0.0, 0.0));
+            tail_net.leaves.push_back(std::move(v));
+        }
+        h.full_open = full.open_edges;
+        err = plan_network(h, nullptr, {}, false, cm, cand.second.n_leaves ? &cand.second : nullptr);
+        if (!err.empty()) {
+            last_err = "head: " + err;
+            continue;
+        }
+        h.tail = std::make_shared<Plan>();
+        Plan& t = *h.tail;
+        t.opts = opts;
+        t.opts.prec = TN_C128;       // contracted once per tn_amplitudes call: full precision
+        t.opts.bighead = 0;
+        t.opts.batch_log2 = 0;
+        t.opts.branch_merge = 0;
+        t.opts.max_log2_size = 40;
+        t.esize = storage_bytes(TN_C128);
+        t.net = std::move(tail_net);
+        t.force_dep.assign(t.net.leaves.size(), 0);
+        t.force_dep.back() = 1;
+        err = plan_network(t, nullptr, {}, true, nullptr);
+        if (!err.empty()) {
+            last_err = "tail: " + err;
+            continue;
+        }
+        h.stats.n_c = n_c;
+        h.stats.n_open = (int)h.full_open.size();
+        h.stats.cmacs_tail = t.stats.cmacs_invariant + t.stats.cmacs_per_slice;
+        h.stats.tail_workspace_bytes = std::max<uint64_t>(t.stats.workspace_bytes, 256);
+        const double cost = h.stats.cmacs_invariant + double(h.stats.n_slices) * h.stats.cmacs_per_slice +
+                            h.stats.cmacs_tail;
+        if (std::getenv("TN_DEBUG_CANDS"))
+            std::fprintf(stderr, "bighead tail %zu: n_c %d cost %.3e\n", (size_t)(&cand - &tails[0]), n_c, cost);
+        if (best < 0 || cost < best) {
+            best = cost;
+            out = std::move(h);
+        }
+    }
+    if (best < 0) return last_err;
     return "";
 }
 

@@ -13,6 +13,7 @@
 #include <complex>
 #include <cstdint>
 #include <functional>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -139,6 +140,13 @@ struct Plan {
     int n_static_slots = 0;         // slots of leaves and invariant tensors come first
     tn_plan_stats stats{};
     double unmerged_cmacs_per_slice = 0;
+    // big-head split: this plan is the head (its open legs are the cut legs
+    // c, its accumulator v_head[c]); `tail` is the tail network plus one leaf
+    // that receives v_head (the last leaf, forced slice-dependent) and whose
+    // root is A[s2]
+    std::shared_ptr<Plan> tail;
+    std::vector<int> full_open;     // open legs of the whole network (amplitude index)
+    std::vector<char> force_dep;    // leaves treated as slice-dependent (their data arrives later)
 };
 
 // Learned step-time model as seen by the planner: predict log(ms) of each

@@ -11,8 +11,10 @@ from . import tn
 
 
 def workspace(plan, device=None):
+    """Workspace for tn_contract_slices and tn_amplitudes (the larger need)."""
     s = plan.stats()
-    return torch.empty(max(int(s["workspace_bytes"]), 256), dtype=torch.uint8, device=device or "cuda")
+    n = max(int(s["workspace_bytes"]), int(s["tail_workspace_bytes"]), 256)
+    return torch.empty(n, dtype=torch.uint8, device=device or "cuda")
 
 
 def accumulator(plan, device=None):

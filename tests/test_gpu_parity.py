@@ -403,3 +403,70 @@ def test_c4_random_circuit_slice_vs_oracle():
     got = _run(p, [j])
     ref = nw.contract(nw.slice_network(net, sliced, nw.slice_values(sliced, j)), tree)
     assert _rel(got, ref) < C64_TOL
+
+
+# --- big-head split: head summed over slices, tail contracted once ---------
+
+@pytest.mark.parametrize("prec,tol", [("c64", C64_TOL), ("c128", C128_TOL)])
+def test_bighead_c1_vs_statevector(prec, tol):
+    w = rqc.workload("c1_tiny_3x4_m8")
+    _say("c1 bighead", prec)
+    p = _plan(w, bighead=1, prec=prec, max_log2_size=5)
+    s = p.stats()
+    assert s["n_c"] > 0 and s["acc_log2"] == s["n_c"]
+    got = _run(p)
+    psi = sv.simulate_numpy(w["circuit"])
+    ref = sv.amplitudes_from_state(psi, 12, w["open_q"], w["fixed_q"], w["bits"])
+    assert got.shape == ref.shape
+    assert _rel(got, ref) < tol
+
+
+def test_bighead_c2_vs_statevector_and_range_split(c2_state):
+    """All slices against the state vector; two ranges summed into one
+    accumulator, and a second tn_amplitudes call on the same plan (the tail's
+    slice-free steps are kept from the first call), give the same amplitudes."""
+    torch = _torch()
+    from paper_2103_03074_amd import runtime
+    w, psi = c2_state
+    p = _plan(w, bighead=1, restarts=4, max_log2_size=22)
+    s = p.stats()
+    _say("c2 bighead: n_c", s["n_c"], "slices", s["n_slices"])
+    assert s["n_slices"] > 1
+    got = _run(p)
+    ref = sv.amplitudes_from_state(psi, 25, w["open_q"], w["fixed_q"], w["bits"])
+    assert _rel(got, ref) < C64_TOL
+    ws = runtime.workspace(p)
+    acc = runtime.accumulator(p)
+    k = s["n_slices"] // 3
+    p.contract_slices(ws, acc, 0, k)
+    p.contract_slices(ws, acc, k, s["n_slices"])
+    amps = torch.empty(2 << s["n_open"], dtype=torch.float64, device="cuda")
+    p.amplitudes(acc, amps, ws)
+    a1 = amps.clone()
+    p.amplitudes(acc, amps, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(a1, amps)
+    assert _rel(torch.view_as_complex(a1.view(-1, 2)).cpu().numpy(), ref) < C64_TOL
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", C128_TOL), ("c64", PRODUCT_C64_TOL)])
+def test_bighead_c3_product_circuit_closed_form(prec, tol):
+    """Bench shape (5x8 grid, 16 cycles, 16 open) with product two-qubit
+    gates: sums over a few head slices, after the tail, against the closed
+    form of the same slices."""
+    w = rqc.workload("c3_5x8_m16", two_qubit="product")
+    p = _plan(w, bighead=1, restarts=4, seed=0, prec=prec)
+    s = p.stats()
+    sliced = p.sliced_edges()
+    assert s["n_c"] > 0 and s["n_open"] == 16
+    n = len(sliced)
+    ids = [int(i) for i in rqc.sample_slice_ids(n, 2, seed=2)]
+    for j in ids:
+        _say("c3 bighead product circuit", prec, "slice", j, "of", s["n_slices"], "n_c", s["n_c"])
+        got = _run(p, (j, j + 1))
+        ref = cf.product_amplitudes(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], sliced, j)
+        assert _rel(got, ref) < tol
+    _say("c3 bighead product circuit", prec, "slice list", ids)
+    got = _run(p, ids)
+    ref = sum(cf.product_amplitudes(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], sliced, j) for j in ids)
+    assert _rel(got, ref) < tol

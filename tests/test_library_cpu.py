@@ -108,11 +108,34 @@ def test_planner_rejects_bad_input(case):
     assert ei.value.status == -1
 
 
-def test_unimplemented_option_is_refused():
+@pytest.mark.parametrize("name,n_open", [("c1_tiny_3x4_m8", None), ("c2_5x5_m16", None), ("c1_tiny_3x4_m8", 0)])
+def test_bighead_split_plans(name, n_open):
+    """Head/tail split: the accumulator is the head's vector over the n_c cut
+    legs; the tail is contracted by tn_amplitudes."""
+    w = rqc.workload(name)
+    o, f, b = list(w["open_q"]), list(w["fixed_q"]), list(w["bits"])
+    if n_open == 0:
+        f, b = sorted(o + f), [1] * (len(o) + len(f))
+        o = []
+    p = tn.Plan(w["circuit"], o, f, b, bighead=1)
+    s = p.stats()
+    assert s["n_open"] == len(o)
+    assert s["acc_log2"] == s["n_c"] and 0 <= s["n_c"] <= 28
+    assert (s["n_c"] > 0) == (len(o) > 0)
+    assert s["tail_workspace_bytes"] >= 256 and (s["cmacs_tail"] > 0) == (len(o) > 0)
+    # sliced edges are edges of the full network, never open legs
+    net = nw.build_network(w["circuit"], o, f, b)
+    for e in p.sliced_edges():
+        assert tuple(e) in net.edges() and tuple(e) not in set(map(tuple, net.open_labels))
+
+
+def test_bighead_refuses_user_tree_or_slicing():
     w = rqc.workload("c1_tiny_3x4_m8")
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    closed = [e for e in net.edges() if e not in set(map(tuple, net.open_labels))]
     with pytest.raises(tn.TnError) as ei:
-        tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], bighead=1)
-    assert ei.value.status == -5 and "bighead" in str(ei.value)
+        tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], bighead=1, sliced=[closed[0]])
+    assert ei.value.status == -1 and "bighead" in str(ei.value)
 
 
 def test_planner_degenerate_networks():
