@@ -421,6 +421,23 @@ def test_bighead_c1_vs_statevector(prec, tol):
     assert _rel(got, ref) < tol
 
 
+def test_bighead_no_open_qubits_vs_statevector():
+    """n_open = 0: the tail is the single v_head leaf (one amplitude)."""
+    w = rqc.workload("c1_tiny_3x4_m8")
+    fixed_q = list(range(12))
+    bits = rqc.fixed_bits(12, seed=4)
+    from paper_2103_03074_amd import tn
+    _say("c1 bighead, no open qubits")
+    p = tn.Plan(w["circuit"], [], fixed_q, bits, bighead=1, max_log2_size=6)
+    s = p.stats()
+    assert s["n_c"] == 0 and s["n_open"] == 0
+    got = _run(p)
+    psi = sv.simulate_numpy(w["circuit"])
+    ref = sv.amplitudes_from_state(psi, 12, [], fixed_q, np.array(bits, dtype=np.uint8))
+    assert got.shape == ref.shape == (1,)
+    assert _rel(got, ref) < C64_TOL
+
+
 def test_bighead_c2_vs_statevector_and_range_split(c2_state):
     """All slices against the state vector; two ranges summed into one
     accumulator, and a second tn_amplitudes call on the same plan (the tail's
