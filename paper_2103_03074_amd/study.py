@@ -11,6 +11,15 @@ estimator is computed the same way for every form, so the XEB differences
 measure precision only).
 
     python -m paper_2103_03074_amd.study --out result.json
+
+With `--bighead` it instead times whole jobs (all slices, then the
+amplitudes call) on the 40-qubit 5x8 / 16-cycle workload, complex64: the
+single tree whose root carries the open legs through every slice, with the
+2^16 slices of the benchmark and with the planner's own slicing, against the
+big-head split (head slices summed into v_head over the cut legs, the tail
+contracted once by the amplitudes call) with the planner's slicing.
+
+    python -m paper_2103_03074_amd.study --bighead --out bighead.json
 """
 
 import argparse
@@ -76,12 +85,60 @@ def precision_study(n_samples=256, precs=("c128", "c64", "split_fp16", "bf16"), 
     return out
 
 
+def bighead_study(restarts=16):
+    import torch
+    import rqc
+    from . import tn, runtime
+    w = rqc.workload("c3_5x8_m16")
+    res = {}
+    modes = (("single_tree_2^16_slices", dict(n_slice_edges=16)),
+             ("single_tree_planner_slicing", dict()),
+             ("bighead_planner_slicing", dict(bighead=1)))
+    for mode, extra in modes:
+        t0 = time.perf_counter()
+        p = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], restarts=restarts, seed=0, branch_merge=1,
+                    **extra)
+        t_plan = time.perf_counter() - t0
+        ws = runtime.workspace(p)
+        acc = runtime.accumulator(p)
+        p.autotune(ws, acc, None, reps=5)          # also sets up the plan on the device
+        s = p.stats()
+        n = s["n_slices"]
+        amps = torch.empty(2 << s["n_open"], dtype=torch.float64, device="cuda")
+        p.amplitudes(acc, amps, ws)                # first tail call prepares the tail
+        torch.cuda.synchronize()
+        acc.zero_()
+        t0 = time.perf_counter()
+        p.contract_slices(ws, acc, 0, n)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p.amplitudes(acc, amps, ws)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        x = tn.xeb(amps, s["n_open"], w["circuit"].n_qubits, 1.0, ks=[1])
+        total = s["cmacs_invariant"] + n * s["cmacs_per_slice"] + s["cmacs_tail"]
+        res[mode] = {"n_slices": n, "batch_log2": s["batch_log2"], "n_c": s["n_c"], "n_open": s["n_open"],
+                     "largest_intermediate_log2": s["max_log2_size"], "plan_seconds": t_plan,
+                     "cmacs_total": total, "cmacs_per_slice": s["cmacs_per_slice"], "cmacs_tail": s["cmacs_tail"],
+                     "contract_seconds": t1 - t0, "amplitudes_call_ms": 1e3 * (t2 - t1),
+                     "job_seconds": t2 - t0, "amplitudes_per_s": 2 ** s["n_open"] / (t2 - t0),
+                     "TFLOP/s": 8.0 * n * s["cmacs_per_slice"] / (t1 - t0) / 1e12,
+                     "F_self": x["F_self"], "F_unif": x["F_unif"]}
+        log(mode, res[mode])
+        p.close()
+    ref = res["single_tree_2^16_slices"]
+    for mode, _ in modes:
+        res[mode]["job_time_vs_single_tree_2^16"] = res[mode]["job_seconds"] / ref["job_seconds"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--samples", type=int, default=256)
+    ap.add_argument("--bighead", action="store_true")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
-    res = precision_study(args.samples)
+    res = bighead_study() if args.bighead else precision_study(args.samples)
     text = json.dumps(res)
     print(text, flush=True)
     if args.out:
