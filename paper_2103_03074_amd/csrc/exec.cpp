@@ -172,7 +172,8 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
                     (panel_tn_log(st.tile) == 6 ? "4>" : "2>");
         hipError_t e;
         if (!panel_fp32(st.tile, p.opts.prec)) {
-            uint32_t* conv = (ws && st.conv_off != ~uint64_t(0))
+            // tile bit 3: split A in registers inside the GEMM (no pass over A)
+            uint32_t* conv = (ws && st.conv_off != ~uint64_t(0) && !(st.tile & 8))
                                  ? reinterpret_cast<uint32_t*>((unsigned char*)ws + st.conv_off * (uint64_t)p.esize)
                                  : nullptr;
             if (name) *name = (conv ? "k_lp_convert_a+k_panel_lp<" : "k_panel_lp<") + name->substr(8);
@@ -505,7 +506,10 @@ std::vector<Candidate> candidates(const Step& st, tn_precision prec) {
     for (int t = 0; t < kNumPanelTiles; ++t)
         if (panel_ok(st.m_log, st.n_log, st.k_log, st.b_log, prec, t)) {
             c.push_back({K_PANEL, t, 0});
-            if (prec != TN_C64) c.push_back({K_PANEL, t | 4, 0});   // FP32 panel in a mixed form
+            if (prec != TN_C64) {
+                c.push_back({K_PANEL, t | 4, 0});   // FP32 panel in a mixed form
+                c.push_back({K_PANEL, t | 8, 0});   // A split in registers, no separate pass
+            }
         }
     c.push_back({K_SMALL, 0, 0});
     if (st.k_log <= 4 && st.n_log <= 4 && st.m_log >= (prec == TN_C128 ? 8 : 9) &&
@@ -599,6 +603,9 @@ std::string autotune(Plan& p, DeviceState& d, void* ws, double* acc, const char*
                 if (!err.empty()) break;
                 std::sort(t.begin(), t.end());
                 const float med = t[t.size() / 2];
+                if (std::getenv("TN_TUNE_LOG"))
+                    std::fprintf(stderr, "tune m%d n%d k%d b%d: kernel %d tile %d %.1f us\n", st.m_log, st.n_log,
+                                 st.k_log, st.b_log, c.kernel, c.tile, 1e3 * med);
                 if (best_ms < 0 || med < best_ms) {
                     best_ms = med;
                     best = c;

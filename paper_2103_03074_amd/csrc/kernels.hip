@@ -907,7 +907,9 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
 // (r, h) supplies eight halves = four packed (re, im) words of complex k
 // 4 h .. 4 h + 3 of an 8-k step, for row r; B' words are staged in LDS k-fastest
 // (rows of real columns: (re, -im) for column 2n, (im, re) for 2n+1).  Split
-// mode runs hi*hi, hi*lo and lo*hi; the result is (acc + 2^-11 accx) * 2^(ea+eb).
+// mode keeps one accumulator for 2^11 a b = (2^11 hi_a) hi_b + hi_a lo_b +
+// lo_a hi_b (2^11 hi_a is exact in FP16: |hi_a| < 1 after scaling); the
+// result is acc * 2^(ea+eb-11).
 template <int KC, int NB, int MODE, bool PRE>
 __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
     constexpr int N = 16 * NB;
@@ -963,17 +965,11 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
             bb[i] = B[(k0 + e / N) * sBk + (e % N)];
         }
     };
-    floatx16 acc[NB], accx[SPLIT ? NB : 1];
+    floatx16 acc[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
-    if constexpr (SPLIT) {
-#pragma unroll
-        for (int nb = 0; nb < (SPLIT ? NB : 1); ++nb)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) accx[nb][v] = 0.f;
-    }
     load_b(0);   // B first: see k_panel
     load_a(av, ph, 0);
     for (uint64_t k0 = 0; k0 < K; k0 += KC) {
@@ -1008,6 +1004,8 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
                 ah = uint4{hw[0], hw[1], hw[2], hw[3]};
                 al = uint4{lw[0], lw[1], lw[2], lw[3]};
             }
+            half8 ah8 = __builtin_bit_cast(half8, ah);
+            if constexpr (SPLIT) ah8 = ah8 * (_Float16)2048.f;   // exact: a power-of-two scaling
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int o = (nb * 32 + r) * RS + 8 * s + 4 * h;
@@ -1016,15 +1014,15 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
                     acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah),
                                                                       __builtin_bit_cast(bf16x8, bh), acc[nb], 0, 0, 0);
                 } else {
-                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, ah),
-                                                                     __builtin_bit_cast(half8, bh), acc[nb], 0, 0, 0);
                     if constexpr (SPLIT) {
                         const uint4 bl = *reinterpret_cast<const uint4*>(&Bw[PL - 1][o]);
-                        accx[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, ah),
-                                                                          __builtin_bit_cast(half8, bl), accx[nb], 0, 0, 0);
-                        accx[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, al),
-                                                                          __builtin_bit_cast(half8, bh), accx[nb], 0, 0, 0);
+                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, ah),
+                                                                         __builtin_bit_cast(half8, bl), acc[nb], 0, 0, 0);
+                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, al),
+                                                                         __builtin_bit_cast(half8, bh), acc[nb], 0, 0, 0);
                     }
+                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, __builtin_bit_cast(half8, bh), acc[nb],
+                                                                     0, 0, 0);
                 }
             }
         }
@@ -1040,7 +1038,7 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
                 for (int i = 0; i < 4; ++i) av[s][i] = an[s][i];
         }
     }
-    const float sc = ldexpf(1.f, ea + eb);
+    const float sc = ldexpf(1.f, ea + eb - (SPLIT ? 11 : 0));
     uint64_t off_lo = 0;
     int src_lo = 0;
     for (int i = 0; i < 8; ++i)
@@ -1058,9 +1056,7 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
         __syncthreads();
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            float x = acc[nb][v];
-            if constexpr (SPLIT) x = fmaf(accx[nb][v], 1.f / 2048.f, x);
-            x *= sc;
+            const float x = acc[nb][v] * sc;
             const int row = w * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
             cs[row * (2 * CS) + r] = x;
             mx = fmaxf(mx, fabsf(x));
