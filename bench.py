@@ -133,7 +133,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3_5x8_m16")
     ap.add_argument("--prec", default="c64")
-    ap.add_argument("--compare", default="", help="second precision timed on the same workload")
+    ap.add_argument("--compare", default="split_fp16",
+                    help="second precision timed on the same workload (\"\" for none)")
     ap.add_argument("--restarts", type=int, default=16)
     ap.add_argument("--batch-log2", type=int, default=-1)
     ap.add_argument("--branch-merge", type=int, default=1,
@@ -204,7 +205,7 @@ def main():
             plan.set_profiling(False)
         cmacs = s["cmacs_per_batch"] * (n >> s["batch_log2"])
         return {"plan": plan, "stats": s, "sec": dt, "cmacs": cmacs, "prof": prof, "xeb": xres,
-                "t_plan": t_plan, "t_warm": t_warm, "n_tuned": n_tuned}
+                "t_plan": t_plan, "t_warm": t_warm, "n_tuned": n_tuned, "amps": amps.clone()}
 
     log(f"workload {args.workload}, precision {args.prec}")
     main_run = run(args.prec, args.steps, args.warmup, True)
@@ -237,7 +238,10 @@ def main():
                           "TFLOP/s": 8.0 * cmp_run["cmacs"] / cmp_run["sec"] / 1e12,
                           "amplitudes_per_s": 2 ** s["n_open"] / cmp_run["sec"],
                           "speedup_vs_main": sec / cmp_run["sec"],
-                          "xeb": {k: cmp_run["xeb"][k] for k in ("F_unif", "F_self")}}
+                          "xeb": {k: cmp_run["xeb"][k] for k in ("F_unif", "F_self")},
+                          "xeb_delta_vs_main": {k: cmp_run["xeb"][k] - main_run["xeb"][k] for k in ("F_unif", "F_self")},
+                          "amplitudes_norm_rel_diff_vs_main": float(torch.linalg.vector_norm(cmp_run["amps"] - main_run["amps"]) /
+                                                                    torch.linalg.vector_norm(main_run["amps"]))}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, main_run["plan"])

@@ -675,6 +675,18 @@ static void fill_stats(Plan& p) {
 }
 
 // Planning pipeline on a built network (out.net, out.opts and out.esize set).
+double dense_step_rate(tn_precision prec) {
+    // dense steps measured on the 40-qubit workload: FP32 MFMA panels about
+    // 110 TFLOP/s, the split-FP16 panel about 200 on compute-bound shapes.
+    // BF16 (245 there) keeps the FP32 figure: its plan re-tuned with 245 ran
+    // 7 % slower per launch group.  FP64 MFMA about half of FP32.
+    switch (prec) {
+        case TN_SPLIT_FP16: return 200e12;
+        case TN_C128: return 55e12;
+        default: return 110e12;
+    }
+}
+
 static std::string plan_network(Plan& out, const tn_tree* tree, const std::vector<int>& user_sliced,
                                 bool fixed_slicing, const CostModel* cm, const Tree* extra = nullptr) {
     const tn_plan_opts& opts = out.opts;
@@ -849,11 +861,12 @@ static std::string plan_network(Plan& out, const tn_tree* tree, const std::vecto
     if (opts.branch_merge && !tree) {
         std::vector<char> in_s(E, 0);
         for (int e : out.sliced) in_s[e] = 1;
-        Tree merged = reconfigure(leaf_legs, out.tree, in_s, opts.max_log2_size, 8, 16, 1, out.esize);
+        const double rate = dense_step_rate(opts.prec);
+        Tree merged = reconfigure(leaf_legs, out.tree, in_s, opts.max_log2_size, 8, 16, 1, out.esize, rate);
         TreeLegs tlm = tree_legs(net, merged);
         if (slice_cost_tl(tlm, merged, in_s).max_log2 <= opts.max_log2_size &&
-            tree_time_estimate(leaf_legs, merged, in_s, out.esize) <
-                tree_time_estimate(leaf_legs, out.tree, in_s, out.esize))
+            tree_time_estimate(leaf_legs, merged, in_s, out.esize, rate) <
+                tree_time_estimate(leaf_legs, out.tree, in_s, out.esize, rate))
             out.tree = merged;
     }
     err = finalize(out);

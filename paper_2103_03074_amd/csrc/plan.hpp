@@ -75,11 +75,15 @@ Tree partition_tree(const std::vector<Legs>& leaf_legs, uint64_t seed, double ep
 // frontier tensors by their optimal order (cost per slice with the edges in
 // in_s removed, intermediates above 2^target penalised).
 // objective 0: complex multiply-adds; 1: roofline time estimate (branch
-// merging).
+// merging) with dense_rate the flop rate of MFMA-shaped steps.
 Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::vector<char>& in_s, int target,
-                 int max_frontier, int passes, int objective = 0, int esize = 8);
+                 int max_frontier, int passes, int objective = 0, int esize = 8, double dense_rate = 110e12);
 // Roofline time estimate of a tree (same units as objective 1).
-double tree_time_estimate(const std::vector<Legs>& leaf_legs, const Tree& t, const std::vector<char>& in_s, int esize);
+double tree_time_estimate(const std::vector<Legs>& leaf_legs, const Tree& t, const std::vector<char>& in_s, int esize,
+                          double dense_rate = 110e12);
+// Measured flop rate (Eq. (3) flops per second) of MFMA-shaped steps per
+// precision on MI355X, for the time objective.
+double dense_step_rate(tn_precision prec);
 
 // Leaves contracted one after another in network (time) order.
 Tree time_order_tree(int n_leaves);

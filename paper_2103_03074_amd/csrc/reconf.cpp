@@ -55,6 +55,7 @@ struct Rebuild {
 // -- under this objective merging two small branches before a large step
 // (appendix B, "GPU efficiency") wins whenever it saves time.
 static double g_esize = 8.0;
+static double g_dense_rate = 110e12;
 static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, int target, int objective) {
     double c;
     if (objective == 0) {
@@ -64,9 +65,10 @@ static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, in
         const int m = a_bits - k, n = b_bits - k;
         const bool dense = std::max(m, n) >= 6 && std::min(m, n) >= 3 && k >= 2;
         const double flops = 8.0 * std::exp2((double)u_bits);
-        // rates measured on MI355X: complex64 MFMA steps ~110 TFLOP/s, VALU
-        // steps ~25 TFLOP/s, streaming steps ~4 TB/s
-        const double rate = dense ? 110e12 : 25e12;
+        // rates measured on MI355X (Eq. (3) flops): MFMA steps ~110 TFLOP/s in
+        // complex64 (higher in the mixed forms, set by the caller), VALU steps
+        // ~25 TFLOP/s, streaming steps ~4 TB/s
+        const double rate = dense ? g_dense_rate : 25e12;
         const double bytes = g_esize * (std::exp2((double)a_bits) + std::exp2((double)b_bits) +
                                         std::exp2((double)out_bits));
         c = std::max(flops / rate, bytes / 4e12) * 1e12 + 2.0e6;   // + per-launch overhead (~2 us)
@@ -77,8 +79,9 @@ static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, in
 
 
 Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::vector<char>& in_s, int target,
-                 int max_frontier, int passes, int objective, int esize) {
+                 int max_frontier, int passes, int objective, int esize, double dense_rate) {
     g_esize = esize;
+    g_dense_rate = dense_rate;
     Tree t = in;
     const int L = t.n_leaves;
     if (t.lhs.empty()) return t;
@@ -234,8 +237,9 @@ Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::
 }
 
 double tree_time_estimate(const std::vector<Legs>& leaf_legs, const Tree& t, const std::vector<char>& in_s,
-                          int esize) {
+                          int esize, double dense_rate) {
     g_esize = esize;
+    g_dense_rate = dense_rate;
     const int L = t.n_leaves;
     std::vector<Legs> legs(t.n_nodes());
     for (int i = 0; i < L; ++i) {
