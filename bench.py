@@ -73,6 +73,23 @@ def dominant_kernel(profile, prec):
     return rec, table
 
 
+def tree_roofline_fraction(profile, prec):
+    """Sum over the timed steps of t_min = max(flops / MFMA peak, bytes / HBM
+    peak), over their summed measured time: the roofline fraction of the whole
+    tree, skinny steps included.  Low-precision GEMM kernels count against the
+    FP16/BF16 peak, everything else against the peak of the storage form."""
+    t_min = t_meas = 0.0
+    for st in profile:
+        if not st["launches"]:
+            continue
+        name = st["kernel_name"] or ""
+        peak = PEAK_TFLOPS["split_fp16"] if "_lp" in name else PEAK_TFLOPS["c128" if prec == "c128" else "c64"]
+        per = max(8.0 * st["cmacs"] / (peak * 1e12), st["bytes"] / (PEAK_HBM_GBS * 1e9))
+        t_min += per * st["launches"]
+        t_meas += st["total_ms"] / 1e3
+    return t_min / t_meas if t_meas > 0 else None
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary of this workload (FETCH_SIZE + WRITE_SIZE, calibrated against a
@@ -204,7 +221,8 @@ def main():
         if profile:
             plan.set_profiling(False)
         cmacs = s["cmacs_per_batch"] * (n >> s["batch_log2"])
-        return {"plan": plan, "stats": s, "sec": dt, "cmacs": cmacs, "prof": prof, "xeb": xres,
+        unmerged = s["cmacs_per_slice_unmerged"] * n + s["cmacs_invariant"]
+        return {"plan": plan, "stats": s, "sec": dt, "cmacs": cmacs, "unmerged": unmerged, "prof": prof, "xeb": xres,
                 "t_plan": t_plan, "t_warm": t_warm, "n_tuned": n_tuned, "amps": amps.clone()}
 
     log(f"workload {args.workload}, precision {args.prec}")
@@ -227,17 +245,21 @@ def main():
         "pct_mfma_peak": 100.0 * tflops / PEAK_TFLOPS[args.prec],
         "amplitudes_per_s": amps_per_s,
         "complex_macs_per_step": main_run["cmacs"],
+        "complex_macs_per_step_unmerged_tree": main_run["unmerged"],
+        "roofline_fraction_tree": tree_roofline_fraction(main_run["prof"], args.prec),
         "xeb": {k: main_run["xeb"][k] for k in ("F_unif", "F_self", "P_s1", "cond_xeb")},
         "roofline": roof,
         "kernels": table,
         "plan_seconds": main_run["t_plan"],
     }
     if args.compare:
-        cmp_run = run(args.compare, args.steps, args.warmup, False)
+        cmp_run = run(args.compare, args.steps, args.warmup, True)
         out["compare"] = {"dtype": args.compare, "ms_per_step": cmp_run["sec"] * 1e3,
                           "TFLOP/s": 8.0 * cmp_run["cmacs"] / cmp_run["sec"] / 1e12,
                           "amplitudes_per_s": 2 ** s["n_open"] / cmp_run["sec"],
                           "speedup_vs_main": sec / cmp_run["sec"],
+                          "roofline_fraction_tree": tree_roofline_fraction(cmp_run["prof"], args.compare),
+                          "dominant_kernel": dominant_kernel(cmp_run["prof"], args.compare)[0],
                           "xeb": {k: cmp_run["xeb"][k] for k in ("F_unif", "F_self")},
                           "xeb_delta_vs_main": {k: cmp_run["xeb"][k] - main_run["xeb"][k] for k in ("F_unif", "F_self")},
                           "amplitudes_norm_rel_diff_vs_main": float(torch.linalg.vector_norm(cmp_run["amps"] - main_run["amps"]) /

@@ -216,6 +216,24 @@ tn_status tn_xeb(const double* d_amps, int32_t n_open, int32_t n_qubits, double 
                  const int64_t* ks, int32_t n_ks, double* h_topk,
                  tn_xeb_result* out, void* hip_stream);
 
+/* Sampling from the conditional distribution of the open qubits (appendix C
+ * defines P(s2 | s1) = P(s1; s2) / P(s1); the conclusion notes that the
+ * method can sample from it): draws n_samples indices s2 (open-qubit
+ * bitstrings, first open qubit the most significant bit, as in d_amps) by
+ * inverse transform.  Sample i is the smallest s2 with
+ * cdf[s2] > d_uniform[i] * cdf[2^n_open - 1], cdf the float64 inclusive
+ * prefix sum of |A[s2]|^2 in index order (summed in a fixed order: results
+ * are bitwise repeatable); if every amplitude is zero, every sample is
+ * 2^n_open - 1.  d_amps: 2^n_open complex128; d_uniform: n_samples doubles
+ * in [0, 1), drawn by the caller; d_out: n_samples uint64; all device
+ * memory owned by the caller.  d_workspace must hold
+ * tn_sample_workspace_bytes(n_open) bytes.  Asynchronous on hip_stream.
+ * TN_EINVAL for NULL pointers (d_uniform and d_out may be NULL when
+ * n_samples is 0), n_open outside [0, 34] or a small workspace. */
+size_t tn_sample_workspace_bytes(int32_t n_open);
+tn_status tn_sample(const double* d_amps, int32_t n_open, const double* d_uniform, uint64_t n_samples,
+                    uint64_t* d_out, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
 /* Per-step timing of the slice-dependent steps, for measurement and for the
  * learned step-time model.  While enabled, tn_contract_slices records HIP
  * events around every step it launches (two event sets used alternately, so

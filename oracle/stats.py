@@ -10,6 +10,9 @@
 * Marginal P(s1) = sum_s2 P(s1; s2) and conditional P(s2 | s1) = P / P(s1)
   (appendix C): P(s1) = (F_unif + 1) 2^-n1, and the conditional
   distribution's own XEB is exactly 0.
+* Sampling from P(s2 | s1) (appendix C; the conclusion notes the method can
+  sample from it) by inverse transform: a uniform u picks the smallest s2
+  whose cumulative probability exceeds u times the total.
 * Porter-Thomas checks: Kolmogorov-Smirnov distance of N p against Exp(1)
   and the second moment E[(N p)^2] = 2.
 * GPU efficiency, Eq. (3): E = 8 * (complex multiply-adds) / (peak * time).
@@ -47,6 +50,16 @@ def marginal(p):
 def conditional(p):
     p = np.asarray(p, dtype=np.float64)
     return p / p.sum()
+
+
+def conditional_samples(p, u):
+    """Inverse-transform samples of the distribution p / sum(p): for each u in
+    [0, 1) the smallest index j with cdf[j] > u * cdf[-1] (cdf the inclusive
+    cumulative sum), clamped to the last index."""
+    p = np.asarray(p, dtype=np.float64)
+    cdf = np.cumsum(p)
+    j = np.searchsorted(cdf, np.asarray(u, dtype=np.float64) * cdf[-1], side="right")
+    return np.minimum(j, p.size - 1).astype(np.int64), cdf
 
 
 def pt_ks_distance(p, n_qubits):

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "exec.hpp"
+#include "sample.hpp"
 #include "mlp.hpp"
 #include "plan.hpp"
 
@@ -253,6 +254,22 @@ tn_status tn_amplitudes(tn_plan_t p, const double* d_acc, double* d_amps, void* 
     const uint64_t n = 2ull << p->plan.root_log2;
     hipError_t e = tn::launch_copy_acc(d_acc, d_amps, n, s);
     if (e != hipSuccess) return fail(TN_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
+    return TN_OK;
+}
+
+size_t tn_sample_workspace_bytes(int32_t n_open) {
+    if (n_open < 0 || n_open > 34) return 0;
+    return sizeof(double) * tn::sample_workspace_elems(1ull << n_open);
+}
+
+tn_status tn_sample(const double* d_amps, int32_t n_open, const double* d_uniform, uint64_t n_samples,
+                    uint64_t* d_out, void* d_workspace, size_t ws_bytes, void* hip_stream) {
+    if (!d_amps || !d_workspace || (n_samples > 0 && (!d_uniform || !d_out))) return fail(TN_EINVAL, "NULL argument");
+    if (n_open < 0 || n_open > 34) return fail(TN_EINVAL, "n_open out of range");
+    if (ws_bytes < tn_sample_workspace_bytes(n_open)) return fail(TN_EINVAL, "workspace smaller than tn_sample_workspace_bytes");
+    hipError_t e = tn::launch_sample(d_amps, 1ull << n_open, d_uniform, n_samples, d_out,
+                                     static_cast<double*>(d_workspace), reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(TN_EDEVICE, std::string("sample: ") + hipGetErrorString(e));
     return TN_OK;
 }
 

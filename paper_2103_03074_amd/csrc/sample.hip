@@ -1,0 +1,155 @@
+// Sampling open-qubit bitstrings s2 from the conditional distribution
+// P(s2 | s1) = |A[s2]|^2 / sum |A|^2 (appendix C; the conclusion notes that
+// the method can sample from this distribution).  Inverse transform: the
+// float64 inclusive prefix sum of |A|^2 in index order is built by a
+// three-pass block scan (per-block scans, a scan of the block sums, then the
+// block offsets added), and each caller-supplied uniform u picks the smallest
+// index j with cdf[j] > u * cdf[L - 1] by binary search.  Every sum is taken
+// in a fixed order, so results are bitwise repeatable.
+#include "sample.hpp"
+
+namespace tn {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;                          // elements per thread
+constexpr int kScanBlock = kScanThreads * kScanPer;  // elements per block
+
+// Inclusive scan of a block's kScanBlock values held kScanPer per thread
+// (thread t holds elements kScanPer t .. kScanPer t + kScanPer - 1); returns
+// the exclusive prefix of thread t's first element and writes the block sum.
+__device__ double block_exclusive_prefix(double mine, double* sh, double& total) {
+    const int t = threadIdx.x;
+    sh[t] = mine;
+    __syncthreads();
+    // Hillis-Steele over the per-thread sums (fixed order of additions)
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        const double v = t >= d ? sh[t - d] : 0.0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    total = sh[kScanThreads - 1];
+    const double excl = t > 0 ? sh[t - 1] : 0.0;
+    __syncthreads();
+    return excl;
+}
+
+// Pass 1 on the amplitudes: cdf[i] = block-local inclusive prefix of |A|^2,
+// sums[b] = the block's total.
+__global__ void __launch_bounds__(kScanThreads) k_prob_scan(const double2* amps, uint64_t n, double* cdf,
+                                                            double* sums) {
+    __shared__ double sh[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanPer;
+    double v[kScanPer];
+    double run = 0.0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        double p = 0.0;
+        if (base + i < n) {
+            const double2 a = amps[base + i];
+            p = a.x * a.x + a.y * a.y;
+        }
+        run += p;
+        v[i] = run;
+    }
+    double total;
+    const double excl = block_exclusive_prefix(run, sh, total);
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i)
+        if (base + i < n) cdf[base + i] = excl + v[i];
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Same on a float64 array in place (the block sums of the level below).
+__global__ void __launch_bounds__(kScanThreads) k_scan(double* x, uint64_t n, double* sums) {
+    __shared__ double sh[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanPer;
+    double v[kScanPer];
+    double run = 0.0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        run += base + i < n ? x[base + i] : 0.0;
+        v[i] = run;
+    }
+    double total;
+    const double excl = block_exclusive_prefix(run, sh, total);
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i)
+        if (base + i < n) x[base + i] = excl + v[i];
+    if (sums && threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Pass 3: x[i] += (inclusive scan of the block sums)[block(i) - 1].
+__global__ void __launch_bounds__(kScanThreads) k_add_offsets(double* x, uint64_t n, const double* scanned_sums) {
+    const uint64_t blk = blockIdx.x;
+    if (blk == 0) return;
+    const double off = scanned_sums[blk - 1];
+    const uint64_t base = blk * kScanBlock + (uint64_t)threadIdx.x * kScanPer;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i)
+        if (base + i < n) x[base + i] += off;
+}
+
+__global__ void __launch_bounds__(256) k_search(const double* cdf, uint64_t n, const double* u, uint64_t n_samples,
+                                                uint64_t* out) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_samples) return;
+    const double target = u[i] * cdf[n - 1];
+    uint64_t lo = 0, hi = n - 1;   // smallest j with cdf[j] > target, clamped to n - 1
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (cdf[mid] > target) hi = mid;
+        else lo = mid + 1;
+    }
+    out[i] = lo;
+}
+
+uint64_t blocks_for(uint64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
+
+}  // namespace
+
+uint64_t sample_workspace_elems(uint64_t n) {
+    uint64_t total = n;
+    for (uint64_t m = blocks_for(n); ; m = blocks_for(m)) {
+        total += m;
+        if (m <= 1) break;
+    }
+    return total;
+}
+
+hipError_t launch_sample(const double* amps, uint64_t n, const double* u, uint64_t n_samples, uint64_t* out,
+                         double* ws, hipStream_t s) {
+    if (n == 0) return hipErrorInvalidValue;
+    // level 0: the cdf itself; level l + 1: the block sums of level l
+    std::vector<std::pair<double*, uint64_t>> lv;
+    double* p = ws;
+    lv.push_back({p, n});
+    p += n;
+    for (uint64_t m = blocks_for(n); ; m = blocks_for(m)) {
+        lv.push_back({p, m});
+        p += m;
+        if (m <= 1) break;
+    }
+    hipLaunchKernelGGL(k_prob_scan, dim3((unsigned)blocks_for(n)), dim3(kScanThreads), 0, s,
+                       reinterpret_cast<const double2*>(amps), n, lv[0].first, lv[1].first);
+    hipError_t e = hipGetLastError();
+    for (size_t l = 1; e == hipSuccess && l + 1 < lv.size(); ++l) {
+        hipLaunchKernelGGL(k_scan, dim3((unsigned)blocks_for(lv[l].second)), dim3(kScanThreads), 0, s, lv[l].first,
+                           lv[l].second, lv[l + 1].first);
+        e = hipGetLastError();
+    }
+    for (size_t l = lv.size() - 1; e == hipSuccess && l-- > 0;) {
+        if (lv[l].second <= (uint64_t)kScanBlock) continue;   // one block: nothing to add
+        hipLaunchKernelGGL(k_add_offsets, dim3((unsigned)blocks_for(lv[l].second)), dim3(kScanThreads), 0, s,
+                           lv[l].first, lv[l].second, lv[l + 1].first);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess || n_samples == 0) return e;
+    hipLaunchKernelGGL(k_search, dim3((unsigned)((n_samples + 255) / 256)), dim3(256), 0, s, lv[0].first, n, u,
+                       n_samples, out);
+    return hipGetLastError();
+}
+
+}  // namespace tn

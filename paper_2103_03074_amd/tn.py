@@ -111,6 +111,8 @@ _SIGS = {
     "tn_xeb": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                               ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(XebResult), _P]),
+    "tn_sample_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "tn_sample": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P, ctypes.c_size_t, _P]),
     "tn_plan_set_profiling": (ctypes.c_int, [_P, ctypes.c_int32]),
     "tn_plan_step_profile": (ctypes.c_int, [_P, ctypes.POINTER(StepProfile), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
@@ -366,6 +368,22 @@ class Mlp:
         fmin = np.ascontiguousarray(fmin, dtype=np.float32)
         fmax = np.ascontiguousarray(fmax, dtype=np.float32)
         _check(library().tn_mlp_set_support(self.handle, _fptr(fmin), _fptr(fmax), fmin.size, float(margin)))
+
+
+def sample_workspace_bytes(n_open):
+    return int(library().tn_sample_workspace_bytes(int(n_open)))
+
+
+def sample(amps, n_open, uniforms, out, ws, stream=None):
+    """Inverse-transform samples of P(s2 | s1) from a device tensor of
+    2^n_open complex128 amplitudes: uniforms (float64) and out (int64, same
+    length) and the workspace ws are caller-owned device tensors."""
+    n = int(uniforms.numel())
+    if int(out.numel()) != n:
+        raise ValueError("out and uniforms must have the same length")
+    _check(library().tn_sample(ctypes.c_void_p(amps.data_ptr()), int(n_open), ctypes.c_void_p(uniforms.data_ptr()),
+                               n, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                               ws.numel() * ws.element_size(), _stream_ptr(stream)))
 
 
 def xeb(amps, n_open, n_qubits, weight=1.0, ks=(), stream=None):

@@ -146,3 +146,11 @@ def test_planner_degenerate_networks():
         p = tn.Plan(c, open_q, fixed_q, [1] * len(fixed_q), n_slice_edges=0)
         s = p.stats()
         assert s["n_open"] == len(open_q) and s["n_slices"] == 1
+
+
+def test_sample_workspace_sizes():
+    """cdf (2^n doubles) plus one double per block of 1024 at every scan level."""
+    assert tn.sample_workspace_bytes(0) == 8 * (1 + 1)
+    assert tn.sample_workspace_bytes(10) == 8 * (1024 + 1)
+    assert tn.sample_workspace_bytes(21) == 8 * (2 ** 21 + 2048 + 2 + 1)
+    assert tn.sample_workspace_bytes(-1) == 0 and tn.sample_workspace_bytes(35) == 0

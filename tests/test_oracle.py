@@ -215,6 +215,41 @@ def test_xeb_identities():
     assert np.isclose(top1, 2.0 ** n * p.max() - 1)
 
 
+def test_conditional_samples_inverse_transform():
+    """Pins for inverse-transform sampling: a hand-worked case, the empirical
+    law on an evenly spaced grid of uniforms (exact counts: grid points fall
+    into the cumulative intervals), zero-probability entries never drawn,
+    and brute force against a linear scan on random probabilities."""
+    p = np.array([0.25, 0.0, 0.25, 0.5])
+    j, _ = stats.conditional_samples(p, [0.0, 0.2499, 0.25, 0.3, 0.4999, 0.5, 0.75, 0.9999])
+    assert j.tolist() == [0, 0, 2, 2, 2, 3, 3, 3]
+    # scaling p does not change the draws (sampling uses p / sum p)
+    j2, _ = stats.conditional_samples(8.0 * p, [0.0, 0.3, 0.5, 0.9999])
+    assert j2.tolist() == [0, 2, 3, 3]
+    # evenly spaced u: the count of index i is the number of grid points in [cdf[i-1], cdf[i])
+    n = 4096
+    u = (np.arange(n) + 0.5) / n
+    j, _ = stats.conditional_samples(p, u)
+    np.testing.assert_array_equal(np.bincount(j, minlength=4), (p * n).astype(int))
+    # brute force: linear scan for the first cumulative sum above u * total
+    rng = np.random.default_rng(5)
+    q = rng.exponential(size=37)
+    q[[3, 10]] = 0.0
+    us = rng.random(500)
+    j, cdf = stats.conditional_samples(q, us)
+    for ui, ji in zip(us, j):
+        t = ui * q.sum()
+        acc, k = 0.0, 0
+        while k < q.size - 1 and acc + q[k] <= t:
+            acc += q[k]
+            k += 1
+        assert ji == k or abs(cdf[ji] - t) < 1e-12 * q.sum() or abs(cdf[ji - 1] - t) < 1e-12 * q.sum()
+        assert q[ji] > 0
+    # all-zero probabilities clamp to the last index
+    j, _ = stats.conditional_samples(np.zeros(8), [0.0, 0.7])
+    assert j.tolist() == [7, 7]
+
+
 @pytest.mark.slow
 def test_porter_thomas_on_25_qubit_state(c2_state):
     _, psi = c2_state
