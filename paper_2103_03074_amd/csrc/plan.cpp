@@ -687,6 +687,22 @@ double dense_step_rate(tn_precision prec) {
     }
 }
 
+// Roofline time estimate (seconds) of the slice-dependent steps of a
+// finalized plan, once per launch group: per launch max(8 cmacs / rate,
+// bytes / 4 TB/s) + 2 us.  Invariant steps run once per plan, not per job,
+// and are left out.
+static double plan_time_estimate(const Plan& p) {
+    const double groups = std::exp2((double)p.sliced.size() - p.batch_log2);
+    const double dense = dense_step_rate(p.opts.prec);
+    double t = 0;
+    for (const Step& st : p.steps) {
+        if (st.invariant) continue;
+        const bool mfma = st.kernel == K_MFMA || st.kernel == K_PANEL || st.kernel == K_SKINNY;
+        t += (std::max(8.0 * st.cmacs / (mfma ? dense : 25e12), st.bytes / 4e12) + 2e-6) * groups;
+    }
+    return t;
+}
+
 static std::string plan_network(Plan& out, const tn_tree* tree, const std::vector<int>& user_sliced,
                                 bool fixed_slicing, const CostModel* cm, const Tree* extra = nullptr) {
     const tn_plan_opts& opts = out.opts;
@@ -866,8 +882,19 @@ static std::string plan_network(Plan& out, const tn_tree* tree, const std::vecto
         TreeLegs tlm = tree_legs(net, merged);
         if (slice_cost_tl(tlm, merged, in_s).max_log2 <= opts.max_log2_size &&
             tree_time_estimate(leaf_legs, merged, in_s, out.esize, rate) <
-                tree_time_estimate(leaf_legs, out.tree, in_s, out.esize, rate))
-            out.tree = merged;
+                tree_time_estimate(leaf_legs, out.tree, in_s, out.esize, rate)) {
+            // the per-slice estimate ignores batch legs (work shared by the
+            // slices of a launch group, outputs that keep the batch legs):
+            // confirm on the executed steps of both trees
+            Plan a = out, b = out;
+            b.tree = merged;
+            std::string ea = finalize(a), eb = finalize(b);
+            if (!ea.empty()) return ea;
+            if (std::getenv("TN_DEBUG_CANDS"))
+                std::fprintf(stderr, "merge: unmerged %.3f ms, merged %.3f ms (estimated)\n",
+                             1e3 * plan_time_estimate(a), eb.empty() ? 1e3 * plan_time_estimate(b) : -1.0);
+            if (eb.empty() && plan_time_estimate(b) < plan_time_estimate(a)) out.tree = merged;
+        }
     }
     err = finalize(out);
     if (!err.empty()) return err;
