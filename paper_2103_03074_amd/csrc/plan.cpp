@@ -687,18 +687,17 @@ double dense_step_rate(tn_precision prec) {
     }
 }
 
-// Roofline time estimate (seconds) of the slice-dependent steps of a
-// finalized plan, once per launch group: per launch max(8 cmacs / rate,
-// bytes / 4 TB/s) + 2 us.  Invariant steps run once per plan, not per job,
-// and are left out.
+// Roofline time estimate (seconds) of one job on a finalized plan: per
+// launch max(8 cmacs / rate, bytes / 4 TB/s) + 2 us, slice-dependent steps
+// once per launch group, invariant steps once.
 static double plan_time_estimate(const Plan& p) {
     const double groups = std::exp2((double)p.sliced.size() - p.batch_log2);
     const double dense = dense_step_rate(p.opts.prec);
     double t = 0;
     for (const Step& st : p.steps) {
-        if (st.invariant) continue;
         const bool mfma = st.kernel == K_MFMA || st.kernel == K_PANEL || st.kernel == K_SKINNY;
-        t += (std::max(8.0 * st.cmacs / (mfma ? dense : 25e12), st.bytes / 4e12) + 2e-6) * groups;
+        const double one = std::max(8.0 * st.cmacs / (mfma ? dense : 25e12), st.bytes / 4e12) + 2e-6;
+        t += st.invariant ? one : one * groups;
     }
     return t;
 }
@@ -884,8 +883,9 @@ static std::string plan_network(Plan& out, const tn_tree* tree, const std::vecto
             tree_time_estimate(leaf_legs, merged, in_s, out.esize, rate) <
                 tree_time_estimate(leaf_legs, out.tree, in_s, out.esize, rate)) {
             // the per-slice estimate ignores batch legs (work shared by the
-            // slices of a launch group, outputs that keep the batch legs):
-            // confirm on the executed steps of both trees
+            // slices of a launch group, outputs that keep the batch legs) and
+            // the slice-invariant part: confirm on the executed steps of both
+            // trees, one whole job each
             Plan a = out, b = out;
             b.tree = merged;
             std::string ea = finalize(a), eb = finalize(b);
