@@ -679,12 +679,8 @@ double dense_step_rate(tn_precision prec) {
     // dense steps measured on the 40-qubit workload: FP32 MFMA panels about
     // 110 TFLOP/s, the split-FP16 panel about 200 on compute-bound shapes.
     // BF16 (245 there) keeps the FP32 figure: its plan re-tuned with 245 ran
-    // 7 % slower per launch group.  FP64 MFMA about half of FP32.
-    switch (prec) {
-        case TN_SPLIT_FP16: return 200e12;
-        case TN_C128: return 55e12;
-        default: return 110e12;
-    }
+    // 7 % slower per launch group.  Complex128 keeps it too (not measured).
+    return prec == TN_SPLIT_FP16 ? 200e12 : 110e12;
 }
 
 // Roofline time estimate (seconds) of one job on a finalized plan: per
