@@ -54,9 +54,14 @@ struct Rebuild {
 // rate for steps large enough for MFMA tiles and a lower VALU rate otherwise
 // -- under this objective merging two small branches before a large step
 // (appendix B, "GPU efficiency") wins whenever it saves time.
-static double g_esize = 8.0;
-static double g_dense_rate = 110e12;
-static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, int target, int objective) {
+struct CostCtx {
+    int objective;       // 0: multiply-adds, 1: roofline time
+    double esize;        // bytes per element
+    double dense_rate;   // flop rate of MFMA-shaped steps
+};
+
+static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, int target, const CostCtx& cx) {
+    const int objective = cx.objective;
     double c;
     if (objective == 0) {
         c = std::exp2((double)u_bits);
@@ -68,8 +73,8 @@ static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, in
         // rates measured on MI355X (Eq. (3) flops): MFMA steps ~110 TFLOP/s in
         // complex64 (higher in the mixed forms, set by the caller), VALU steps
         // ~25 TFLOP/s, streaming steps ~4 TB/s
-        const double rate = dense ? g_dense_rate : 25e12;
-        const double bytes = g_esize * (std::exp2((double)a_bits) + std::exp2((double)b_bits) +
+        const double rate = dense ? cx.dense_rate : 25e12;
+        const double bytes = cx.esize * (std::exp2((double)a_bits) + std::exp2((double)b_bits) +
                                         std::exp2((double)out_bits));
         c = std::max(flops / rate, bytes / 4e12) * 1e12 + 2.0e6;   // + per-launch overhead (~2 us)
     }
@@ -80,8 +85,7 @@ static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, in
 
 Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::vector<char>& in_s, int target,
                  int max_frontier, int passes, int objective, int esize, double dense_rate) {
-    g_esize = esize;
-    g_dense_rate = dense_rate;
+    const CostCtx cx{objective, (double)esize, dense_rate};
     Tree t = in;
     const int L = t.n_leaves;
     if (t.lhs.empty()) return t;
@@ -102,8 +106,7 @@ Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::
             right[c] = b;
             legs[c] = set_xor(legs[a], legs[b]);
             int u = (int)set_union(legs[a], legs[b]).size();
-            cost[c] = step_cost_obj(u, (int)legs[a].size(), (int)legs[b].size(), (int)legs[c].size(), target,
-                                    objective);
+            cost[c] = step_cost_obj(u, (int)legs[a].size(), (int)legs[b].size(), (int)legs[c].size(), target, cx);
         }
         // subtree cost (sum over the subtree)
         std::vector<double> sub(N, 0.0);
@@ -175,7 +178,7 @@ Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::
                     const int b = m ^ a;
                     const int u = (sm[a] | sm[b]).count();
                     const double c = best[a] + best[b] +
-                                     step_cost_obj(u, sm[a].count(), sm[b].count(), sm[m].count(), target, objective);
+                                     step_cost_obj(u, sm[a].count(), sm[b].count(), sm[m].count(), target, cx);
                     if (bc < 0 || c < bc) {
                         bc = c;
                         bs = a;
@@ -238,8 +241,7 @@ Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::
 
 double tree_time_estimate(const std::vector<Legs>& leaf_legs, const Tree& t, const std::vector<char>& in_s,
                           int esize, double dense_rate) {
-    g_esize = esize;
-    g_dense_rate = dense_rate;
+    const CostCtx cx{1, (double)esize, dense_rate};
     const int L = t.n_leaves;
     std::vector<Legs> legs(t.n_nodes());
     for (int i = 0; i < L; ++i) {
@@ -252,7 +254,7 @@ double tree_time_estimate(const std::vector<Legs>& leaf_legs, const Tree& t, con
         const int a = t.lhs[s], b = t.rhs[s], c = L + (int)s;
         legs[c] = set_xor(legs[a], legs[b]);
         const int u = (int)set_union(legs[a], legs[b]).size();
-        tot += step_cost_obj(u, (int)legs[a].size(), (int)legs[b].size(), (int)legs[c].size(), 1000, 1);
+        tot += step_cost_obj(u, (int)legs[a].size(), (int)legs[b].size(), (int)legs[c].size(), 1000, cx);
     }
     return tot;
 }

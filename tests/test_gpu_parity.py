@@ -344,6 +344,35 @@ def test_c3_mixed_precision_slice_vs_oracle(prec):
     assert err < MIXED_TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["c64", "split_fp16"])
+def test_c3_autotuned_kernels_slice_vs_oracle(prec):
+    """The bench's configuration: plan, autotune every step shape on a real
+    launch group, then one slice against the oracle (the autotuner may pick
+    split-in-register or pre-split panels, FP32 panels in the mixed form, the
+    skinny kernel or the streaming kernel per shape)."""
+    from paper_2103_03074_amd import runtime
+    w = rqc.workload("c3_5x8_m16")
+    p = _c3_plan(w, prec=prec)
+    ws = runtime.workspace(p)
+    scratch = runtime.accumulator(p)
+    _say("c3 autotune", prec)
+    assert p.autotune(ws, scratch, None, reps=2) > 0
+    del scratch
+    ex = p.export()
+    tiles = sorted({(st["kernel"], st["tile"]) for st in ex["steps"] if not st["invariant"]})
+    _say("c3 autotuned kernels", prec, tiles)
+    sliced = [tuple(e) for e in ex["sliced"]]
+    tree = list(zip(ex["lhs"], ex["rhs"]))
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    j = int(rqc.sample_slice_ids(16, 1, seed=3)[0])
+    _say("c3 autotuned", prec, "slice", j)
+    got = _run(p, (j, j + 1))
+    ref = nw.contract(nw.slice_network(net, sliced, nw.slice_values(sliced, j)), tree)
+    err = _rel(got, ref)
+    _say("c3 autotuned", prec, "norm-rel error", err)
+    assert err < (C64_TOL if prec == "c64" else MIXED_TOL[prec])
+
+
 def test_autotune_keeps_results_and_caches(tmp_path):
     torch = _torch()
     from paper_2103_03074_amd import runtime
