@@ -154,3 +154,24 @@ def test_sample_workspace_sizes():
     assert tn.sample_workspace_bytes(10) == 8 * (1024 + 1)
     assert tn.sample_workspace_bytes(21) == 8 * (2 ** 21 + 2048 + 2 + 1)
     assert tn.sample_workspace_bytes(-1) == 0 and tn.sample_workspace_bytes(35) == 0
+
+
+def test_branch_merging_judged_per_launch_group():
+    """Branch merging is kept only if the executed steps of one whole job get
+    faster.  On the 25-qubit workload all 2^8 slices share one launch group;
+    the per-slice estimate alone once merged its tree to 100x the
+    multiply-adds (37 ms per job against 4.9 ms unmerged on MI355X)."""
+    w = rqc.workload("c2_5x5_m16")
+    kw = dict(restarts=16, n_slice_edges=8, seed=0)
+    plain = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], branch_merge=0, **kw).stats()
+    merged = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], branch_merge=1, **kw).stats()
+    assert merged["batch_log2"] == 8
+    assert merged["cmacs_per_batch"] <= 2 * plain["cmacs_per_batch"]
+    # the 40-qubit bench plan does merge: more multiply-adds, fewer bytes
+    w3 = rqc.workload("c3_5x8_m16")
+    kw3 = dict(restarts=16, n_slice_edges=16, seed=0)
+    p0 = tn.Plan(w3["circuit"], w3["open_q"], w3["fixed_q"], w3["bits"], branch_merge=0, **kw3).stats()
+    p1 = tn.Plan(w3["circuit"], w3["open_q"], w3["fixed_q"], w3["bits"], branch_merge=1, **kw3).stats()
+    g0 = p0["n_slices"] >> p0["batch_log2"]
+    g1 = p1["n_slices"] >> p1["batch_log2"]
+    assert p1["bytes_per_batch"] * g1 < p0["bytes_per_batch"] * g0
