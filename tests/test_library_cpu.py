@@ -156,7 +156,7 @@ def test_sample_workspace_sizes():
     assert tn.sample_workspace_bytes(-1) == 0 and tn.sample_workspace_bytes(35) == 0
 
 
-def test_branch_merging_judged_per_launch_group():
+def test_branch_merging_decided_per_launch_group():
     """Branch merging is kept only if the executed steps of one whole job get
     faster.  On the 25-qubit workload all 2^8 slices share one launch group;
     the per-slice estimate alone once merged its tree to 100x the
