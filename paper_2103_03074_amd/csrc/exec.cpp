@@ -167,19 +167,24 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
     }
     if (st.kernel == K_PANEL) {
         g.tn = panel_tn_log(st.tile);
-        if (name)
-            *name = std::string("k_panel<") + (panel_kc_log(st.tile) == 5 ? "32," : "16,") +
-                    (panel_tn_log(st.tile) == 6 ? "4>" : "2>");
+        // names as profilers show the device functions (template arguments)
+        const std::string kcnb = std::string(panel_kc_log(st.tile) == 5 ? "32," : "16,") +
+                                 (panel_tn_log(st.tile) == 6 ? "4," : "2,");
+        const bool nt = st.tile & 16;
         hipError_t e;
         if (!panel_fp32(st.tile, p.opts.prec)) {
             // tile bit 3: split A in registers inside the GEMM (no pass over A)
             uint32_t* conv = (ws && st.conv_off != ~uint64_t(0) && !(st.tile & 8))
                                  ? reinterpret_cast<uint32_t*>((unsigned char*)ws + st.conv_off * (uint64_t)p.esize)
                                  : nullptr;
-            if (name) *name = (conv ? "k_lp_convert_a+k_panel_lp<" : "k_panel_lp<") + name->substr(8);
-            e = launch_panel_lp(mode, st.tile & 3, g, conv, s);
+            const int lt = conv ? (st.tile & 3) : (st.tile & 19);
+            if (name)
+                *name = std::string(conv ? "k_lp_convert_a+" : "") + "k_panel_lp<" + kcnb + std::to_string(mode) +
+                        (conv ? ",true," : ",false,") + (!conv && nt ? "true>" : "false>");
+            e = launch_panel_lp(mode, lt, g, conv, s);
         } else {
-            e = launch_panel(st.tile & 3, g, s);
+            if (name) *name = "k_panel<" + kcnb + (nt ? "true>" : "false>");
+            e = launch_panel(st.tile & 19, g, s);
         }
         if (e != hipSuccess) return std::string("panel launch: ") + hipGetErrorString(e);
         return "";
@@ -506,9 +511,13 @@ std::vector<Candidate> candidates(const Step& st, tn_precision prec) {
     for (int t = 0; t < kNumPanelTiles; ++t)
         if (panel_ok(st.m_log, st.n_log, st.k_log, st.b_log, prec, t)) {
             c.push_back({K_PANEL, t, 0});
-            if (prec != TN_C64) {
-                c.push_back({K_PANEL, t | 4, 0});   // FP32 panel in a mixed form
-                c.push_back({K_PANEL, t | 8, 0});   // A split in registers, no separate pass
+            if (prec == TN_C64) {
+                c.push_back({K_PANEL, t | 16, 0});   // non-temporal A loads
+            } else {
+                c.push_back({K_PANEL, t | 4, 0});        // FP32 panel in a mixed form
+                c.push_back({K_PANEL, t | 4 | 16, 0});
+                c.push_back({K_PANEL, t | 8, 0});        // A split in registers, no separate pass
+                c.push_back({K_PANEL, t | 8 | 16, 0});
             }
         }
     c.push_back({K_SMALL, 0, 0});

@@ -594,7 +594,7 @@ __global__ void __launch_bounds__(256) k_skinny(GemmArgs g) {
 // the 128 x 16 output slabs are staged in LDS and written in C-address order
 // (tile bits m0..m6, n0..n3 in the epilogue decode).  Tiles are visited in
 // the XCD-aware order of tile_index (tm = 7, tn = 4 + log2 NB).
-template <int KC, int NB>
+template <int KC, int NB, bool NT>
 __global__ void __launch_bounds__(256) k_panel(GemmArgs g) {
     constexpr int N = 16 * NB;
     constexpr int KP = KC / 2;
@@ -612,10 +612,18 @@ __global__ void __launch_bounds__(256) k_panel(GemmArgs g) {
     const int r = lane & 31, h = lane >> 5;
     const uint64_t K = 1ull << g.k_log;
     float2 a[KP], an[KP], bb[PBN];
+    // NT: A is streamed with non-temporal loads (it is read by few N tiles)
     auto load_a = [&](float2* dst, uint64_t k0) {
         const float2* src = A + w * 32 + r + (k0 + h) * sAk;
 #pragma unroll
-        for (int p = 0; p < KP; ++p) dst[p] = src[(uint64_t)(2 * p) * sAk];
+        for (int p = 0; p < KP; ++p) {
+            if constexpr (NT) {
+                const floatv2 t = __builtin_nontemporal_load(reinterpret_cast<const floatv2*>(src + (uint64_t)(2 * p) * sAk));
+                dst[p] = make_float2(t.x, t.y);
+            } else {
+                dst[p] = src[(uint64_t)(2 * p) * sAk];
+            }
+        }
     };
     auto load_b = [&](uint64_t k0) {
 #pragma unroll
@@ -910,7 +918,7 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
 // mode keeps one accumulator for 2^11 a b = (2^11 hi_a) hi_b + hi_a lo_b +
 // lo_a hi_b (2^11 hi_a is exact in FP16: |hi_a| < 1 after scaling); the
 // result is acc * 2^(ea+eb-11).
-template <int KC, int NB, int MODE, bool PRE>
+template <int KC, int NB, int MODE, bool PRE, bool NT>
 __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
     constexpr int N = 16 * NB;
     constexpr int NR = 2 * N;
@@ -955,7 +963,15 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
 #pragma unroll
             for (int s = 0; s < NS; ++s)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) dst[s][i] = src[(uint64_t)(8 * s + i) * sAk];
+                for (int i = 0; i < 4; ++i) {
+                    if constexpr (NT) {   // non-temporal: A is read by few N tiles
+                        const floatv2 t = __builtin_nontemporal_load(
+                            reinterpret_cast<const floatv2*>(src + (uint64_t)(8 * s + i) * sAk));
+                        dst[s][i] = make_float2(t.x, t.y);
+                    } else {
+                        dst[s][i] = src[(uint64_t)(8 * s + i) * sAk];
+                    }
+                }
         }
     };
     auto load_b = [&](uint64_t k0) {
@@ -1306,19 +1322,26 @@ hipError_t launch_skinny(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <bool NT>
+static void launch_panel_t(int tile, const GemmArgs& g, dim3 grid, hipStream_t s) {
+    switch (tile & 3) {
+        case 0: hipLaunchKernelGGL((k_panel<32, 4, NT>), grid, dim3(256), 0, s, g); break;
+        case 1: hipLaunchKernelGGL((k_panel<16, 4, NT>), grid, dim3(256), 0, s, g); break;
+        case 2: hipLaunchKernelGGL((k_panel<32, 2, NT>), grid, dim3(256), 0, s, g); break;
+        default: hipLaunchKernelGGL((k_panel<16, 2, NT>), grid, dim3(256), 0, s, g); break;
+    }
+}
+
 hipError_t launch_panel(int tile, const GemmArgs& g, hipStream_t s) {
-    // tile: bit 0 -> KC = 16 (else 32), bit 1 -> NB = 2 (else 4)
+    // tile: bit 0 -> KC = 16 (else 32), bit 1 -> NB = 2 (else 4), bit 4 ->
+    // non-temporal A loads
     const int kc_log = (tile & 1) ? 4 : 5, nb_log = (tile & 2) ? 1 : 2;
-    if (tile < 0 || tile > 3 || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) || g.k_log < kc_log ||
+    if (tile < 0 || (tile & ~19) || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) || g.k_log < kc_log ||
         g.ep_n != 11 || g.split_log != 0)
         return hipErrorInvalidValue;
     const dim3 grid = grid_for(tile_blocks(g));
-    switch (tile) {
-        case 0: hipLaunchKernelGGL((k_panel<32, 4>), grid, dim3(256), 0, s, g); break;
-        case 1: hipLaunchKernelGGL((k_panel<16, 4>), grid, dim3(256), 0, s, g); break;
-        case 2: hipLaunchKernelGGL((k_panel<32, 2>), grid, dim3(256), 0, s, g); break;
-        default: hipLaunchKernelGGL((k_panel<16, 2>), grid, dim3(256), 0, s, g); break;
-    }
+    if (tile & 16) launch_panel_t<true>(tile, g, grid, s);
+    else launch_panel_t<false>(tile, g, grid, s);
     return hipGetLastError();
 }
 
@@ -1343,26 +1366,32 @@ static hipError_t launch_lp(int tile, const GemmArgs& g, dim3 grid, hipStream_t 
     return hipGetLastError();
 }
 
-template <int MODE, bool PRE>
+template <int MODE, bool PRE, bool NT>
 static hipError_t launch_panel_lp_t(int tile, const GemmArgs& g, dim3 grid, hipStream_t s) {
-    switch (tile) {
-        case 0: hipLaunchKernelGGL((k_panel_lp<32, 4, MODE, PRE>), grid, dim3(256), 0, s, g); break;
-        case 1: hipLaunchKernelGGL((k_panel_lp<16, 4, MODE, PRE>), grid, dim3(256), 0, s, g); break;
-        case 2: hipLaunchKernelGGL((k_panel_lp<32, 2, MODE, PRE>), grid, dim3(256), 0, s, g); break;
-        default: hipLaunchKernelGGL((k_panel_lp<16, 2, MODE, PRE>), grid, dim3(256), 0, s, g); break;
+    switch (tile & 3) {
+        case 0: hipLaunchKernelGGL((k_panel_lp<32, 4, MODE, PRE, NT>), grid, dim3(256), 0, s, g); break;
+        case 1: hipLaunchKernelGGL((k_panel_lp<16, 4, MODE, PRE, NT>), grid, dim3(256), 0, s, g); break;
+        case 2: hipLaunchKernelGGL((k_panel_lp<32, 2, MODE, PRE, NT>), grid, dim3(256), 0, s, g); break;
+        default: hipLaunchKernelGGL((k_panel_lp<16, 2, MODE, PRE, NT>), grid, dim3(256), 0, s, g); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_panel_lp(int mode, int tile, const GemmArgs& g, uint32_t* conv, hipStream_t s) {
+    // tile bits as in launch_panel; bit 4 (non-temporal A loads) applies to
+    // A split in registers (conv = null) only
     const int kc_log = (tile & 1) ? 4 : 5, nb_log = (tile & 2) ? 1 : 2;
-    if (tile < 0 || tile > 3 || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) || g.k_log < kc_log ||
-        g.ep_n != 11 || g.split_log != 0 || (mode != LP_SPLIT_FP16 && mode != LP_BF16))
+    if (tile < 0 || (tile & ~19) || (conv && (tile & 16)) || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) ||
+        g.k_log < kc_log || g.ep_n != 11 || g.split_log != 0 || (mode != LP_SPLIT_FP16 && mode != LP_BF16))
         return hipErrorInvalidValue;
     const dim3 grid = grid_for(tile_blocks(g));
     if (!conv) {
-        if (mode == LP_SPLIT_FP16) return launch_panel_lp_t<LP_SPLIT_FP16, false>(tile, g, grid, s);
-        return launch_panel_lp_t<LP_BF16, false>(tile, g, grid, s);
+        const bool nt = tile & 16;
+        if (mode == LP_SPLIT_FP16)
+            return nt ? launch_panel_lp_t<LP_SPLIT_FP16, false, true>(tile, g, grid, s)
+                      : launch_panel_lp_t<LP_SPLIT_FP16, false, false>(tile, g, grid, s);
+        return nt ? launch_panel_lp_t<LP_BF16, false, true>(tile, g, grid, s)
+                  : launch_panel_lp_t<LP_BF16, false, false>(tile, g, grid, s);
     }
     // one pass over A into word planes, then the GEMM on the planes
     const uint64_t na = 1ull << (g.m_log + g.b_log + g.k_log);
@@ -1377,8 +1406,8 @@ hipError_t launch_panel_lp(int mode, int tile, const GemmArgs& g, uint32_t* conv
     h.A = hi;
     h.a_lo = lo;
     h.sa_n = 0;   // the planes are already slice-selected
-    if (mode == LP_SPLIT_FP16) return launch_panel_lp_t<LP_SPLIT_FP16, true>(tile, h, grid, s);
-    return launch_panel_lp_t<LP_BF16, true>(tile, h, grid, s);
+    if (mode == LP_SPLIT_FP16) return launch_panel_lp_t<LP_SPLIT_FP16, true, false>(tile, h, grid, s);
+    return launch_panel_lp_t<LP_BF16, true, false>(tile, h, grid, s);
 }
 
 hipError_t launch_fill(float* p, uint64_t n, hipStream_t s) {
