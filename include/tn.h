@@ -33,6 +33,10 @@
  *    their qubit, trailing ones backward into the last, |0> into the first
  *    and the projector <s1_q| into the last two-qubit gate of qubit q.
  *  - Slice j fixes the i-th sliced edge to bit i of j.
+ *  - A plan keeps device state (leaves, slice-invariant tensors, the tail of
+ *    the big-head split, profiling events): calls on one plan must not run
+ *    concurrently, from several host threads or on several streams at once.
+ *    Different plans are independent; planning itself is re-entrant.
  */
 #ifndef TN_H
 #define TN_H
