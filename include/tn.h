@@ -272,6 +272,21 @@ tn_status tn_plan_step_profile(tn_plan_t p, tn_step_profile* out, int32_t cap, i
 tn_status tn_plan_autotune(tn_plan_t p, void* d_workspace, size_t ws_bytes, double* d_acc_scratch,
                            const char* cache_path, int32_t reps, int32_t* n_tuned, void* hip_stream);
 
+/* Kernel configurations that can run step `step` (index into the plan's
+ * steps in execution order, as listed by tn_plan_export_json): up to cap
+ * (kernel, tile) pairs are written to h_kernels / h_tiles (host arrays owned
+ * by the caller), their number to *n.  Split-K is offered only while the
+ * step uses it. */
+tn_status tn_plan_step_candidates(tn_plan_t p, int32_t step, int32_t* h_kernels, int32_t* h_tiles,
+                                  int32_t cap, int32_t* n);
+
+/* Run step `step` with one of its candidate configurations from now on
+ * (overrides the planner's or the autotuner's choice; a captured graph is
+ * rebuilt at the next launch).  A slice-invariant step already computed on
+ * the device keeps its result.  TN_EINVAL if (kernel, tile) is not a
+ * candidate; TN_ESTATE while step timing is enabled. */
+tn_status tn_plan_set_step_kernel(tn_plan_t p, int32_t step, int32_t kernel, int32_t tile);
+
 /* ---- learned step-time model ------------------------------------------
  * A 3-layer perceptron d_in -> hidden -> hidden -> 1 (ReLU) on the device,
  * FP32, that maps step features to log(step milliseconds).  Forward,

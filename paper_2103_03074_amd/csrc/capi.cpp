@@ -410,6 +410,35 @@ tn_status tn_plan_autotune(tn_plan_t p, void* d_workspace, size_t ws_bytes, doub
     }
 }
 
+tn_status tn_plan_step_candidates(tn_plan_t p, int32_t step, int32_t* h_kernels, int32_t* h_tiles, int32_t cap,
+                                  int32_t* n) {
+    if (!p || !n || (cap > 0 && (!h_kernels || !h_tiles))) return fail(TN_EINVAL, "NULL argument");
+    if (step < 0 || step >= (int)p->plan.steps.size()) return fail(TN_EINVAL, "step out of range");
+    try {
+        const auto c = tn::step_candidates(p->plan, step);
+        *n = (int32_t)c.size();
+        for (int32_t i = 0; i < cap && i < (int32_t)c.size(); ++i) {
+            h_kernels[i] = c[i].first;
+            h_tiles[i] = c[i].second;
+        }
+        return TN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(TN_ENOMEM, "host allocation failed");
+    }
+}
+
+tn_status tn_plan_set_step_kernel(tn_plan_t p, int32_t step, int32_t kernel, int32_t tile) {
+    if (!p) return fail(TN_EINVAL, "NULL argument");
+    if (p->dev.prof.on) return fail(TN_ESTATE, "disable step timing before changing kernels");
+    try {
+        const std::string e = tn::set_step_kernel(p->plan, p->dev, step, kernel, tile);
+        if (!e.empty()) return fail(TN_EINVAL, e);
+        return TN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(TN_ENOMEM, "host allocation failed");
+    }
+}
+
 tn_status tn_step_features(int32_t m_log, int32_t n_log, int32_t k_log, int32_t b_log, int32_t kernel,
                            tn_precision prec, float* out) {
     if (!out) return fail(TN_EINVAL, "NULL argument");

@@ -649,6 +649,29 @@ std::string autotune(Plan& p, DeviceState& d, void* ws, double* acc, const char*
     return "";
 }
 
+std::vector<std::pair<int, int>> step_candidates(const Plan& p, int step) {
+    std::vector<std::pair<int, int>> out;
+    if (step < 0 || step >= (int)p.steps.size()) return out;
+    for (const Candidate& c : candidates(p.steps[step], p.opts.prec)) out.push_back({c.kernel, c.tile});
+    return out;
+}
+
+std::string set_step_kernel(Plan& p, DeviceState& d, int step, int kernel, int tile) {
+    if (step < 0 || step >= (int)p.steps.size()) return "step out of range";
+    Step& st = p.steps[step];
+    bool ok = false;
+    for (const Candidate& c : candidates(st, p.opts.prec)) ok |= c.kernel == kernel && c.tile == tile;
+    if (!ok) return "not a candidate configuration of this step";
+    if (kernel != K_SPLITK) st.splitk_log = 0;
+    st.kernel = kernel;
+    st.tile = tile;
+    if (d.gexec) {   // the captured graph used the old choice
+        (void)hipGraphExecDestroy(d.gexec);
+        d.gexec = nullptr;
+    }
+    return "";
+}
+
 void release(DeviceState& d) {
     if (d.gexec) (void)hipGraphExecDestroy(d.gexec);
     if (d.cap_stream) (void)hipStreamDestroy(d.cap_stream);

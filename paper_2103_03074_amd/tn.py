@@ -111,6 +111,10 @@ _SIGS = {
     "tn_xeb": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                               ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(XebResult), _P]),
+    "tn_plan_step_candidates": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int32)]),
+    "tn_plan_set_step_kernel": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "tn_sample_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "tn_sample": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P, ctypes.c_size_t, _P]),
     "tn_plan_set_profiling": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -260,6 +264,19 @@ class Plan:
         arr = (StepProfile * max(1, n.value))()
         _check(library().tn_plan_step_profile(self.handle, arr, n.value, ctypes.byref(n)))
         return [arr[i].to_dict() for i in range(n.value)]
+
+    def step_candidates(self, step):
+        """(kernel, tile) configurations that can run step `step` (index into
+        export()["steps"])."""
+        n = ctypes.c_int32()
+        _check(library().tn_plan_step_candidates(self.handle, int(step), None, None, 0, ctypes.byref(n)))
+        ks = (ctypes.c_int32 * max(1, n.value))()
+        ts = (ctypes.c_int32 * max(1, n.value))()
+        _check(library().tn_plan_step_candidates(self.handle, int(step), ks, ts, n.value, ctypes.byref(n)))
+        return [(ks[i], ts[i]) for i in range(n.value)]
+
+    def set_step_kernel(self, step, kernel, tile):
+        _check(library().tn_plan_set_step_kernel(self.handle, int(step), int(kernel), int(tile)))
 
     def autotune(self, ws, acc_scratch, cache_path=None, reps=5, stream=None):
         n = ctypes.c_int32()

@@ -373,6 +373,37 @@ def test_c3_autotuned_kernels_slice_vs_oracle(prec):
     assert err < (C64_TOL if prec == "c64" else MIXED_TOL[prec])
 
 
+@pytest.mark.parametrize("prec", ["c64", "split_fp16", "bf16"])
+def test_c3_every_kernel_configuration_of_dense_steps(prec):
+    """Each configuration the autotuner may choose (MFMA tiles, FP32 panels
+    with and without non-temporal loads, low-precision panels on pre-split or
+    register-split A, the VALU kernel) is
+    forced in turn on two slice-dependent dense steps of the bench plan (the
+    largest, and the first panel step); one slice each time against the
+    oracle."""
+    w = rqc.workload("c3_5x8_m16")
+    p = _c3_plan(w, prec=prec)
+    ex = p.export()
+    dep = [i for i, st in enumerate(ex["steps"]) if not st["invariant"] and st["kernel"] in (1, 5)]
+    big = max(dep, key=lambda i: ex["steps"][i]["cmacs"])
+    first_panel = next(i for i in dep if ex["steps"][i]["kernel"] == 5)
+    sliced = [tuple(e) for e in ex["sliced"]]
+    tree = list(zip(ex["lhs"], ex["rhs"]))
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    j = int(rqc.sample_slice_ids(16, 1, seed=4)[0])
+    ref = nw.contract(nw.slice_network(net, sliced, nw.slice_values(sliced, j)), tree)
+    tol = C64_TOL if prec == "c64" else MIXED_TOL[prec]
+    for step in sorted({big, first_panel}):
+        st = ex["steps"][step]
+        orig = (st["kernel"], st["tile"])
+        for kernel, tile in p.step_candidates(step):
+            _say("c3", prec, "step", step, (st["m"], st["n"], st["k"], st["batch"]), "kernel", kernel, "tile", tile)
+            p.set_step_kernel(step, kernel, tile)
+            got = _run(p, (j, j + 1))
+            assert _rel(got, ref) < tol, (step, kernel, tile)
+        p.set_step_kernel(step, *orig)
+
+
 def test_autotune_keeps_results_and_caches(tmp_path):
     torch = _torch()
     from paper_2103_03074_amd import runtime

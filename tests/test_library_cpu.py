@@ -175,3 +175,24 @@ def test_branch_merging_decided_per_launch_group():
     g0 = p0["n_slices"] >> p0["batch_log2"]
     g1 = p1["n_slices"] >> p1["batch_log2"]
     assert p1["bytes_per_batch"] * g1 < p0["bytes_per_batch"] * g0
+
+
+def test_step_candidates_and_forcing():
+    w = rqc.workload("c3_5x8_m16")
+    p = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], prec="split_fp16", n_slice_edges=16, restarts=4,
+                seed=0, branch_merge=1)
+    ex = p.export()
+    i = next(k for k, st in enumerate(ex["steps"]) if st["kernel"] == 5)
+    cands = p.step_candidates(i)
+    assert (ex["steps"][i]["kernel"], ex["steps"][i]["tile"]) in cands
+    # mixed panels: pre-split, FP32, FP32 non-temporal, register-split (and non-temporal) per base tile
+    tiles = {t for k, t in cands if k == 5}
+    assert {0, 4, 20, 8, 24} <= tiles
+    k, t = cands[-1]
+    p.set_step_kernel(i, k, t)
+    assert (p.export()["steps"][i]["kernel"], p.export()["steps"][i]["tile"]) == (k, t)
+    with pytest.raises(tn.TnError) as ei:
+        p.set_step_kernel(i, 5, 999)
+    assert ei.value.status == -1
+    with pytest.raises(tn.TnError):
+        p.set_step_kernel(len(ex["steps"]), 0, 0)
