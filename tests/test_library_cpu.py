@@ -196,3 +196,15 @@ def test_step_candidates_and_forcing():
     assert ei.value.status == -1
     with pytest.raises(tn.TnError):
         p.set_step_kernel(len(ex["steps"]), 0, 0)
+
+
+def test_sample_argument_errors_before_any_launch():
+    """tn_sample validates its arguments on the host: no device is touched."""
+    import ctypes
+    lib = tn.library()
+    fake = ctypes.c_void_p(16)   # never dereferenced: every case fails validation first
+    assert lib.tn_sample(None, 4, fake, 1, fake, fake, 1 << 20, None) == -1            # NULL amplitudes
+    assert lib.tn_sample(fake, 4, None, 1, fake, fake, 1 << 20, None) == -1            # NULL uniforms
+    assert lib.tn_sample(fake, 35, fake, 1, fake, fake, 1 << 40, None) == -1           # n_open too large
+    assert lib.tn_sample(fake, 10, fake, 1, fake, fake, tn.sample_workspace_bytes(10) - 8, None) == -1
+    assert "workspace" in lib.tn_last_error().decode()
