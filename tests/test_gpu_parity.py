@@ -547,3 +547,20 @@ def test_bighead_c3_product_circuit_closed_form(prec, tol):
     got = _run(p, ids)
     ref = sum(cf.product_amplitudes(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], sliced, j) for j in ids)
     assert _rel(got, ref) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", C128_TOL), ("c64", PRODUCT_C64_TOL_53)])
+def test_bighead_c4_product_circuit_closed_form(prec, tol):
+    """Big-head split at the 53-qubit / 20-cycle shape (20 open qubits, a cut
+    of about 21 legs, 2^32 head slices at the 2^30 target): one head slice
+    through the tail against the closed form of the same slice."""
+    w = rqc.workload("c4_diag53_m20", two_qubit="product")
+    p = _plan(w, bighead=1, restarts=8, seed=0, prec=prec)
+    s = p.stats()
+    sliced = p.sliced_edges()
+    assert s["n_c"] > 0 and s["n_open"] == 20 and s["max_log2_size"] <= 30
+    j = int(rqc.sample_slice_ids(len(sliced), 1, seed=2)[0])
+    _say("c4 bighead product circuit", prec, "slice", j, "of 2 ^", len(sliced), "n_c", s["n_c"])
+    got = _run(p, [j])
+    ref = cf.product_amplitudes(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], sliced, j)
+    assert _rel(got, ref) < tol
