@@ -8,6 +8,8 @@
 // in a fixed order, so results are bitwise repeatable.
 #include "sample.hpp"
 
+#include <algorithm>
+
 namespace tn {
 
 namespace {
@@ -94,16 +96,17 @@ __global__ void __launch_bounds__(kScanThreads) k_add_offsets(double* x, uint64_
 
 __global__ void __launch_bounds__(256) k_search(const double* cdf, uint64_t n, const double* u, uint64_t n_samples,
                                                 uint64_t* out) {
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n_samples) return;
-    const double target = u[i] * cdf[n - 1];
-    uint64_t lo = 0, hi = n - 1;   // smallest j with cdf[j] > target, clamped to n - 1
-    while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (cdf[mid] > target) hi = mid;
-        else lo = mid + 1;
+    const double total = cdf[n - 1];
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n_samples; i += (uint64_t)gridDim.x * 256) {
+        const double target = u[i] * total;
+        uint64_t lo = 0, hi = n - 1;   // smallest j with cdf[j] > target, clamped to n - 1
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (cdf[mid] > target) hi = mid;
+            else lo = mid + 1;
+        }
+        out[i] = lo;
     }
-    out[i] = lo;
 }
 
 uint64_t blocks_for(uint64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
@@ -147,8 +150,8 @@ hipError_t launch_sample(const double* amps, uint64_t n, const double* u, uint64
         e = hipGetLastError();
     }
     if (e != hipSuccess || n_samples == 0) return e;
-    hipLaunchKernelGGL(k_search, dim3((unsigned)((n_samples + 255) / 256)), dim3(256), 0, s, lv[0].first, n, u,
-                       n_samples, out);
+    const uint64_t sb = std::min<uint64_t>((n_samples + 255) / 256, 1u << 20);   // grid-stride beyond that
+    hipLaunchKernelGGL(k_search, dim3((unsigned)sb), dim3(256), 0, s, lv[0].first, n, u, n_samples, out);
     return hipGetLastError();
 }
 
