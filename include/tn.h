@@ -272,6 +272,21 @@ tn_status tn_plan_step_profile(tn_plan_t p, tn_step_profile* out, int32_t cap, i
 tn_status tn_plan_autotune(tn_plan_t p, void* d_workspace, size_t ws_bytes, double* d_acc_scratch,
                            const char* cache_path, int32_t reps, int32_t* n_tuned, void* hip_stream);
 
+/* Open qubits read off a contraction order (section "Big-head simulation of
+ * quantum circuits": the order is found first and the open qubits are chosen
+ * from it).  The network with every qubit closed is planned with `opts`
+ * (NULL = defaults); a qubit ends at its last two-qubit gate, or at its own
+ * node if it has none.  Among the tree's nodes with at most half of the
+ * leaves under them whose subtree holds the ends of at least n_open qubits,
+ * the one with the fewest legs to the rest of the network (ties: the fewest
+ * leaves) is the tail (the whole network if there is none); the n_open lowest-id qubits
+ * ending under it are written to h_open (ascending; caller-owned host array
+ * of n_open) and its leg count, the head-tail cut when exactly these qubits
+ * are opened, to *n_cut.  Host only.  TN_EINVAL for a bad circuit, NULL
+ * pointers or n_open outside [1, min(n_qubits, 40)]. */
+tn_status tn_choose_open_qubits(const tn_circuit* c, int32_t n_open, const tn_plan_opts* opts, int32_t* h_open,
+                                int32_t* n_cut);
+
 /* Kernel configurations that can run step `step` (index into the plan's
  * steps in execution order, as listed by tn_plan_export_json): up to cap
  * (kernel, tile) pairs are written to h_kernels / h_tiles (host arrays owned

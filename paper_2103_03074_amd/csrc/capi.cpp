@@ -410,6 +410,23 @@ tn_status tn_plan_autotune(tn_plan_t p, void* d_workspace, size_t ws_bytes, doub
     }
 }
 
+tn_status tn_choose_open_qubits(const tn_circuit* c, int32_t n_open, const tn_plan_opts* opts, int32_t* h_open,
+                                int32_t* n_cut) {
+    if (!c || !h_open || !n_cut) return fail(TN_EINVAL, "NULL argument");
+    try {
+        std::vector<int> open;
+        int cut = 0;
+        const std::string e =
+            tn::choose_open_qubits(*c, n_open, opts ? *opts : tn::default_opts(), open, cut);
+        if (!e.empty()) return fail(TN_EINVAL, e);
+        for (size_t i = 0; i < open.size(); ++i) h_open[i] = open[i];
+        *n_cut = cut;
+        return TN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(TN_ENOMEM, "host allocation failed");
+    }
+}
+
 tn_status tn_plan_step_candidates(tn_plan_t p, int32_t step, int32_t* h_kernels, int32_t* h_tiles, int32_t cap,
                                   int32_t* n) {
     if (!p || !n || (cap > 0 && (!h_kernels || !h_tiles))) return fail(TN_EINVAL, "NULL argument");

@@ -1158,6 +1158,73 @@ std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
     return "";
 }
 
+// Open qubits read off a contraction order (section "Big-head simulation of
+// quantum circuits": the order is found first, then the open qubits are
+// chosen from it).  The network with every qubit closed is ordered like any
+// other; each qubit ends at its last two-qubit gate (or at its own node if it
+// has none).  Among the tree nodes with at most half of the leaves under them
+// whose subtree holds the ends of at least n_open qubits, the one with the
+// fewest legs to the rest of the network (ties: fewest leaves) is the tail; n_open of its qubits (lowest ids) are opened, and its
+// leg count is the head-tail cut.
+std::string choose_open_qubits(const tn_circuit& c, int n_open, const tn_plan_opts& opts, std::vector<int>& open_out,
+                               int& cut_out) {
+    const int n = c.n_qubits;
+    if (n <= 0 || n > 4096) return "n_qubits out of range";
+    if (n_open < 1 || n_open > std::min(n, 40)) return "n_open out of range";
+    Plan p;
+    p.opts = opts;
+    p.opts.bighead = 0;
+    if (p.opts.prec < TN_C64 || p.opts.prec > TN_BF16) return "unknown precision";
+    if (p.opts.max_log2_size < 1 || p.opts.max_log2_size > 40) return "max_log2_size out of range";
+    p.esize = storage_bytes(p.opts.prec);
+    std::vector<int> all(n);
+    for (int q = 0; q < n; ++q) all[q] = q;
+    std::string err = build_network(c, {}, all, std::vector<uint8_t>(n, 0), p.net);
+    if (!err.empty()) return err;
+    std::vector<int> end_leaf(n, -1);
+    int n2 = 0;
+    for (int g = 0; g < c.n_gates; ++g)
+        if (c.gates[g].q1 >= 0) {
+            end_leaf[c.gates[g].q0] = end_leaf[c.gates[g].q1] = n2;
+            ++n2;
+        }
+    int extra = 0;
+    for (int q = 0; q < n; ++q)
+        if (end_leaf[q] < 0) end_leaf[q] = n2 + extra++;
+    if ((int)p.net.leaves.size() != n2 + extra) return "internal error: leaf count";
+    err = plan_network(p, nullptr, {}, false, nullptr);
+    if (!err.empty()) return err;
+    const Tree& t = p.tree;
+    const int L = t.n_leaves, N = t.n_nodes();
+    const TreeLegs tl = tree_legs(p.net, t);
+    std::vector<int> ends(N, 0), leaves(N, 0);
+    for (int q = 0; q < n; ++q) ends[end_leaf[q]]++;
+    for (int i = 0; i < L; ++i) leaves[i] = 1;
+    for (int k = 0; k < (int)t.lhs.size(); ++k) {
+        ends[L + k] = ends[t.lhs[k]] + ends[t.rhs[k]];
+        leaves[L + k] = leaves[t.lhs[k]] + leaves[t.rhs[k]];
+    }
+    int best = -1;
+    for (int v = 0; v < N; ++v) {
+        // the tail is the small side: at most half of the leaves
+        if (ends[v] < n_open || 2 * leaves[v] > L) continue;
+        if (N == 1) break;
+        const size_t cut = tl.node[v].size();
+        if (best < 0 || cut < tl.node[best].size() || (cut == tl.node[best].size() && leaves[v] < leaves[best]))
+            best = v;
+    }
+    if (best < 0) best = t.root();   // no subtree of at most half the leaves holds enough ends
+    std::vector<char> under(N, 0);
+    under[best] = 1;
+    for (int k = (int)t.lhs.size() - 1; k >= 0; --k)
+        if (under[L + k]) under[t.lhs[k]] = under[t.rhs[k]] = 1;
+    open_out.clear();
+    for (int q = 0; q < n && (int)open_out.size() < n_open; ++q)
+        if (under[end_leaf[q]]) open_out.push_back(q);
+    cut_out = (int)tl.node[best].size();
+    return "";
+}
+
 // ------------------------------------------------------------------- JSON
 
 std::string plan_to_json(const Plan& p) {

@@ -167,6 +167,13 @@ std::string make_plan(const tn_circuit& c, const std::vector<int>& open_q,
                       const tn_tree* tree, const tn_edge* sliced, int n_sliced,
                       const tn_plan_opts& opts, Plan& out, const CostModel* cm = nullptr);
 
+// Open qubits chosen from a contraction order of the closed network (the
+// qubits ending under the node with the fewest legs that holds n_open
+// qubit ends); cut_out receives that node's leg count.
+std::string choose_open_qubits(const tn_circuit& c, int n_open, const tn_plan_opts& opts, std::vector<int>& open_out,
+                               int& cut_out);
+
+
 void step_features(int m, int n, int k, int b, int kernel, int esize, float* out);
 constexpr int kStepFeatures = 12;
 

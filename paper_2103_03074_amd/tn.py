@@ -111,6 +111,8 @@ _SIGS = {
     "tn_xeb": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                               ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(XebResult), _P]),
+    "tn_choose_open_qubits": (ctypes.c_int, [ctypes.POINTER(CircuitC), ctypes.c_int32, ctypes.POINTER(PlanOpts),
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "tn_plan_step_candidates": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                                ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                                ctypes.POINTER(ctypes.c_int32)]),
@@ -187,6 +189,18 @@ def plan_options(prec="c64", max_log2_size=30, n_slice_edges=-1, batch_log2=-1, 
     return PlanOpts(PRECISIONS[prec] if isinstance(prec, str) else int(prec), max_log2_size, n_slice_edges,
                     batch_log2, branch_merge, bighead, restarts, cost_model, seed, max_workspace_bytes,
                     model.handle if model is not None else None)
+
+
+def choose_open_qubits(circuit, n_open, **opts):
+    """Open qubits read off a contraction order of the closed network, and the
+    head-tail cut they give (host only)."""
+    c, keep = _circuit_c(circuit)
+    o = plan_options(**opts)
+    out = (ctypes.c_int32 * max(1, int(n_open)))()
+    cut = ctypes.c_int32()
+    _check(library().tn_choose_open_qubits(ctypes.byref(c), int(n_open), ctypes.byref(o), out, ctypes.byref(cut)))
+    del keep
+    return [out[i] for i in range(int(n_open))], cut.value
 
 
 def _stream_ptr(stream):

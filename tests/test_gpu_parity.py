@@ -564,3 +564,20 @@ def test_bighead_c4_product_circuit_closed_form(prec, tol):
     got = _run(p, [j])
     ref = cf.product_amplitudes(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], sliced, j)
     assert _rel(got, ref) < tol
+
+
+def test_bighead_with_open_qubits_read_off_the_order(c2_state):
+    """Open qubits chosen from a contraction order of the closed 25-qubit
+    network, then the big-head split of that choice, against the state
+    vector."""
+    from paper_2103_03074_amd import tn
+    w, psi = c2_state
+    oq, cut = tn.choose_open_qubits(w["circuit"], 10, restarts=8, seed=0)
+    fq = [q for q in range(25) if q not in set(oq)]
+    bits = rqc.fixed_bits(len(fq), seed=1)
+    p = tn.Plan(w["circuit"], oq, fq, bits, bighead=1, restarts=4, max_log2_size=22)
+    s = p.stats()
+    _say("c2 bighead, open qubits from the order", oq, "node cut", cut, "n_c", s["n_c"])
+    got = _run(p)
+    ref = sv.amplitudes_from_state(psi, 25, oq, fq, np.array(bits, dtype=np.uint8))
+    assert _rel(got, ref) < C64_TOL

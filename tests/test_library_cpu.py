@@ -208,3 +208,25 @@ def test_sample_argument_errors_before_any_launch():
     assert lib.tn_sample(fake, 35, fake, 1, fake, fake, 1 << 40, None) == -1           # n_open too large
     assert lib.tn_sample(fake, 10, fake, 1, fake, fake, tn.sample_workspace_bytes(10) - 8, None) == -1
     assert "workspace" in lib.tn_last_error().decode()
+
+
+def test_open_qubits_read_off_the_order():
+    # two halves that never interact: a half is a subtree with no legs to the rest
+    lay = rqc.rect_layout(2, 3)
+    c = rqc.random_circuit(lay, 6, seed=3)
+    half = {0, 1, 2}
+    c.gates = [g for g in c.gates if len(g.qubits) == 1 or (set(g.qubits) <= half or not set(g.qubits) & half)]
+    oq, cut = tn.choose_open_qubits(c, 3, restarts=4, seed=0)
+    assert cut == 0 and set(oq) in ({0, 1, 2}, {3, 4, 5})
+    # the 40-qubit circuit: distinct, sorted, in range; the big-head split of
+    # the chosen set plans and its cut is no larger than the node's leg count
+    w = rqc.workload("c3_5x8_m16")
+    oq, cut = tn.choose_open_qubits(w["circuit"], 16, restarts=8, seed=0)
+    assert oq == sorted(set(oq)) and len(oq) == 16 and 0 <= oq[0] and oq[-1] < 40 and cut > 0
+    f = [q for q in range(40) if q not in set(oq)]
+    s = tn.Plan(w["circuit"], oq, f, [0] * len(f), bighead=1, restarts=8, seed=0).stats()
+    assert s["n_open"] == 16 and 0 < s["n_c"] <= cut
+    for bad in (0, 41):
+        with pytest.raises(tn.TnError) as ei:
+            tn.choose_open_qubits(w["circuit"], bad)
+        assert ei.value.status == -1
