@@ -17,7 +17,9 @@ amplitudes call) on the 40-qubit 5x8 / 16-cycle workload, complex64: the
 single tree whose root carries the open legs through every slice, with the
 2^16 slices of the benchmark and with the planner's own slicing, against the
 big-head split (head slices summed into v_head over the cut legs, the tail
-contracted once by the amplitudes call) with the planner's slicing.
+contracted once by the amplitudes call) with the planner's slicing, and the
+big-head split of open qubits read off a contraction order of the closed
+network (tn_choose_open_qubits).
 
     python -m paper_2103_03074_amd.study --bighead --out bighead.json
 """
@@ -91,13 +93,20 @@ def bighead_study(restarts=16):
     from . import tn, runtime
     w = rqc.workload("c3_5x8_m16")
     res = {}
-    modes = (("single_tree_2^16_slices", dict(n_slice_edges=16)),
-             ("single_tree_planner_slicing", dict()),
-             ("bighead_planner_slicing", dict(bighead=1)))
-    for mode, extra in modes:
+    # the last mode opens the qubits read off a contraction order of the
+    # closed network instead of the workload's region (another subspace of
+    # the same circuit, same fixed-bit seed)
+    oq, _ = tn.choose_open_qubits(w["circuit"], len(w["open_q"]), restarts=restarts, seed=0)
+    fq = [q for q in range(w["circuit"].n_qubits) if q not in set(oq)]
+    spaces = {"region": (w["open_q"], w["fixed_q"], w["bits"]), "order": (oq, fq, rqc.fixed_bits(len(fq), seed=1))}
+    modes = (("single_tree_2^16_slices", "region", dict(n_slice_edges=16)),
+             ("single_tree_planner_slicing", "region", dict()),
+             ("bighead_planner_slicing", "region", dict(bighead=1)),
+             ("bighead_open_qubits_from_order", "order", dict(bighead=1)))
+    for mode, space, extra in modes:
+        o_q, f_q, bits = spaces[space]
         t0 = time.perf_counter()
-        p = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], restarts=restarts, seed=0, branch_merge=1,
-                    **extra)
+        p = tn.Plan(w["circuit"], o_q, f_q, bits, restarts=restarts, seed=0, branch_merge=1, **extra)
         t_plan = time.perf_counter() - t0
         ws = runtime.workspace(p)
         acc = runtime.accumulator(p)
@@ -126,8 +135,9 @@ def bighead_study(restarts=16):
                      "F_self": x["F_self"], "F_unif": x["F_unif"]}
         log(mode, res[mode])
         p.close()
+    res["bighead_open_qubits_from_order"]["open_qubits"] = [int(q) for q in oq]
     ref = res["single_tree_2^16_slices"]
-    for mode, _ in modes:
+    for mode, _, _ in modes:
         res[mode]["job_time_vs_single_tree_2^16"] = res[mode]["job_seconds"] / ref["job_seconds"]
     return res
 
