@@ -232,13 +232,12 @@ tn_status tn_amplitudes(tn_plan_t p, const double* d_acc, double* d_amps, void* 
             tn::Plan& tp = p->tail->plan;
             std::string err = tn::prepare(tp, p->tail->dev, s);   // tail-only steps, once
             if (!err.empty()) return fail(TN_EDEVICE, err);
-            std::vector<double> h(2ull << n_c);
-            hipError_t e = hipMemcpyAsync(h.data(), d_acc, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+            // interleaved float64 (re, im) has the layout of std::complex<double>
+            std::vector<tn::cd> v(size_t(1) << n_c);
+            hipError_t e = hipMemcpyAsync(v.data(), d_acc, sizeof(tn::cd) * v.size(), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) return fail(TN_EDEVICE, std::string("v_head download: ") + hipGetErrorString(e));
-            std::vector<tn::cd> v(size_t(1) << n_c);
-            for (size_t i = 0; i < v.size(); ++i) v[i] = tn::cd(h[2 * i], h[2 * i + 1]);
-            err = tn::upload_leaf(tp, p->tail->dev, tp.tree.n_leaves - 1, v, s);
+            err = tn::upload_leaf(tp, p->tail->dev, tp.tree.n_leaves - 1, std::move(v), s);
             if (!err.empty()) return fail(TN_EDEVICE, err);
             if ((e = hipMemsetAsync(d_amps, 0, sizeof(double) * (2ull << n_open), s)) != hipSuccess)
                 return fail(TN_EDEVICE, std::string("amplitudes: ") + hipGetErrorString(e));

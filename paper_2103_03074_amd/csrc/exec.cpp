@@ -313,13 +313,14 @@ std::string prepare(Plan& p, DeviceState& d, hipStream_t s) {
     return "";
 }
 
-std::string upload_leaf(Plan& p, DeviceState& d, int leaf, const std::vector<cd>& data, hipStream_t s) {
+std::string upload_leaf(Plan& p, DeviceState& d, int leaf, std::vector<cd> data, hipStream_t s) {
     if (!d.prepared) return "plan not prepared";
     if (leaf < 0 || leaf >= p.tree.n_leaves) return "leaf out of range";
     const size_t n = size_t(1) << p.nodes[leaf].layout.size();
     if (data.size() != n || p.net.leaves[leaf].data.size() != n) return "leaf data size mismatch";
-    HostTensor h = p.net.leaves[leaf];
-    h.data = data;
+    HostTensor h;
+    h.legs = p.net.leaves[leaf].legs;
+    h.data = std::move(data);
     std::vector<unsigned char> host(n * (size_t)p.esize);
     put_leaf(h, p.nodes[leaf].layout, storage_of(p.opts.prec), host.data());
     TN_HIP(hipMemcpyAsync((unsigned char*)d.plan_mem + p.nodes[leaf].off * (uint64_t)p.esize, host.data(), host.size(),

@@ -51,7 +51,7 @@ std::string prepare(Plan& p, DeviceState& d, hipStream_t s);
 std::vector<std::pair<int, int>> step_candidates(const Plan& p, int step);
 std::string set_step_kernel(Plan& p, DeviceState& d, int step, int kernel, int tile);
 // Replace the data of a leaf (natural order of its legs) in prepared plan memory.
-std::string upload_leaf(Plan& p, DeviceState& d, int leaf, const std::vector<cd>& data, hipStream_t s);
+std::string upload_leaf(Plan& p, DeviceState& d, int leaf, std::vector<cd> data, hipStream_t s);
 std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std::vector<Group>& groups,
                        hipStream_t s);
 void release(DeviceState& d);
