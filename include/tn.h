@@ -143,6 +143,7 @@ typedef struct {
                                      outside its training support (FLOP count used) */
     int32_t n_candidates;         /* candidate trees/slicings ranked */
     double predicted_ms;          /* learned model's predicted time of the whole job (0 if unused) */
+    uint64_t graph_replays;       /* launch groups replayed from a captured graph on this plan so far */
 } tn_plan_stats;
 
 typedef struct {
@@ -186,10 +187,18 @@ tn_status tn_plan_export_json(tn_plan_t p, char* buf, size_t cap, size_t* need);
 
 /* Contract slices [slice_begin, slice_end) and add their sum, in float64, to
  * the accumulator d_acc (2^acc_log2 complex128, caller-zeroed before the
- * first call).  Sums over disjoint ranges add up to the sum over their
- * union.  d_workspace must hold stats.workspace_bytes.  The first call on a
- * device uploads the plan's leaves and computes its slice-invariant
- * subtrees.  Errors: TN_EINVAL (range, sizes, NULL), TN_EDEVICE. */
+ * first call).  Section "The algorithm": slicing turns the network into
+ * independent subtasks, one per assignment of the sliced edges, whose results
+ * add up to the unsliced result; appendix B ("Computation details") sums the
+ * final tensors of the subtasks.  Slice j fixes the i-th sliced edge to bit
+ * i of j.  Sums over disjoint ranges add up to the sum over their union.
+ * Runs of at least two full launch groups (2^batch_log2 slices each) replay
+ * one captured HIP graph; other groups, and every group while per-step
+ * profiling is on, are launched one kernel at a time (same kernels, bitwise
+ * equal results).  d_workspace must hold stats.workspace_bytes.  The first
+ * call on a device uploads the plan's leaves and computes its
+ * slice-invariant subtrees.  Asynchronous on hip_stream.
+ * Errors: TN_EINVAL (range, sizes, NULL), TN_EDEVICE. */
 tn_status tn_contract_slices(tn_plan_t p, void* d_workspace, size_t ws_bytes,
                              double* d_acc, uint64_t slice_begin, uint64_t slice_end,
                              void* hip_stream);
@@ -205,7 +214,10 @@ tn_status tn_contract_slice_list(tn_plan_t p, void* d_workspace, size_t ws_bytes
  * v_head . v_tail(s2)): the accumulator is copied to the host, placed as the
  * tail's last leaf and the tail contracted on hip_stream, which is
  * synchronised (the tail's slice-free steps run at the first call only).
- * Without the split the accumulator already holds A and is copied.
+ * Cost of the split form: two stream synchronisations and a round trip of
+ * 2^n_c complex128 through host memory (16 MiB for a 20-leg cut), once per
+ * job, not per slice.  Without the split the accumulator already holds A and
+ * is copied on the device (asynchronous).
  * d_workspace must hold stats.tail_workspace_bytes (TN_EINVAL otherwise). */
 tn_status tn_amplitudes(tn_plan_t p, const double* d_acc, double* d_amps,
                         void* d_workspace, size_t ws_bytes, void* hip_stream);
@@ -215,7 +227,10 @@ tn_status tn_amplitudes(tn_plan_t p, const double* d_acc, double* d_amps,
  * (appendix C).  `weight` multiplies every probability first (1 for full
  * amplitudes; 2^k / |S| for partial sums over a sample S of slices).  If
  * n_ks > 0, h_topk[i] receives the XEB of the ks[i] largest probabilities
- * (post-selection curve of section "Fidelity").  Synchronises the stream. */
+ * (post-selection curve of section "Fidelity").  Synchronises the stream.
+ * TN_EINVAL for NULL pointers, n_open outside [0, 40], n_qubits below
+ * n_open or above 1023 (2^n_qubits must be a finite double), a
+ * non-positive weight or a top-k size outside [1, 2^n_open]. */
 tn_status tn_xeb(const double* d_amps, int32_t n_open, int32_t n_qubits, double weight,
                  const int64_t* ks, int32_t n_ks, double* h_topk,
                  tn_xeb_result* out, void* hip_stream);

@@ -86,3 +86,13 @@ def norm_rel_error(x, ref):
     x = np.asarray(x)
     ref = np.asarray(ref)
     return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+
+def max_err_over_rms(x, ref):
+    """max_i |x_i - ref_i| / sqrt(mean_i |ref_i|^2): the largest single error
+    measured against the typical amplitude (elementwise relative error is
+    ill-posed where Porter-Thomas amplitudes come close to zero)."""
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+    return float(np.max(np.abs(x - ref)) / rms)

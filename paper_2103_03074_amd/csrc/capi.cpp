@@ -111,6 +111,7 @@ tn_status tn_plan(const tn_circuit* c, const int32_t* open_q, int32_t n_open, co
 tn_status tn_plan_stats_get(tn_plan_t p, tn_plan_stats* out) {
     if (!p || !out) return fail(TN_EINVAL, "NULL argument");
     *out = p->plan.stats;
+    out->graph_replays = p->dev.graph_replays;
     return TN_OK;
 }
 
@@ -275,7 +276,8 @@ tn_status tn_sample(const double* d_amps, int32_t n_open, const double* d_unifor
 tn_status tn_xeb(const double* d_amps, int32_t n_open, int32_t n_qubits, double weight, const int64_t* ks,
                  int32_t n_ks, double* h_topk, tn_xeb_result* out, void* hip_stream) {
     if (!d_amps || !out) return fail(TN_EINVAL, "NULL argument");
-    if (n_open < 0 || n_open > 40 || n_qubits < n_open || n_qubits > 4096) return fail(TN_EINVAL, "bad sizes");
+    // 2^n_qubits must be a finite double (Eq. (1) scales by it)
+    if (n_open < 0 || n_open > 40 || n_qubits < n_open || n_qubits > 1023) return fail(TN_EINVAL, "bad sizes");
     if (n_ks < 0 || (n_ks > 0 && (!ks || !h_topk))) return fail(TN_EINVAL, "bad top-k arrays");
     if (!(weight > 0)) return fail(TN_EINVAL, "weight must be positive");
     const uint64_t L = 1ull << n_open;

@@ -80,8 +80,12 @@ int leaf_select(const Plan& p, int node, uint8_t* bit, uint8_t* pos) {
     return n;
 }
 
+// always_max: write the output's max-magnitude slot whatever kernel consumes
+// it (slice-invariant tensors are computed once, before autotuning or a forced
+// configuration may move their consumer to a low-precision MFMA kernel).
 std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, const void* A, const void* B, void* C,
-                        void* ws, hipStream_t s, std::string* name = nullptr, const uint64_t* d_slice = nullptr) {
+                        void* ws, hipStream_t s, std::string* name = nullptr, const uint64_t* d_slice = nullptr,
+                        bool always_max = false) {
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
     g.A = A;
@@ -101,7 +105,7 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
         const int parent = p.nodes[st.node].parent;
         if (parent >= 0 && p.step_of_node[parent] >= 0) {
             const int ck = p.steps[p.step_of_node[parent]].kernel;
-            if (ck == K_MFMA || ck == K_PANEL) g.cmax = d.d_max + p.nodes[st.node].slot;
+            if (always_max || ck == K_MFMA || ck == K_PANEL) g.cmax = d.d_max + p.nodes[st.node].slot;
         }
     }
     const int mode = lp_mode(p.opts.prec);
@@ -234,6 +238,17 @@ std::string profile_harvest_set(DeviceState& d, int set) {
 
 }  // namespace
 
+// Destroy the captured graph once every replay queued from it has finished:
+// its kernel nodes' argument buffers belong to the executable graph.
+static std::string drop_graph(DeviceState& d) {
+    if (!d.gexec) return "";
+    hipError_t e = d.g_done ? hipEventSynchronize(d.g_done) : hipSuccess;
+    (void)hipGraphExecDestroy(d.gexec);
+    d.gexec = nullptr;
+    if (e != hipSuccess) return std::string("hipEventSynchronize: ") + hipGetErrorString(e);
+    return "";
+}
+
 std::string profile_harvest(DeviceState& d) {
     std::string e = profile_harvest_set(d, 0);
     if (!e.empty()) return e;
@@ -302,7 +317,7 @@ std::string prepare(Plan& p, DeviceState& d, hipStream_t s) {
         void* B = node_ptr(p, d, nullptr, st.b_node, 0);
         void* C = (unsigned char*)d.plan_mem + st.c_off * (uint64_t)p.esize;
         if (st.kernel == K_SPLITK) return "split-K step in the slice-invariant part needs a workspace";
-        std::string err = launch_step(p, d, st, A, B, C, nullptr, s);
+        std::string err = launch_step(p, d, st, A, B, C, nullptr, s, nullptr, nullptr, true);
         if (!err.empty()) return err;
     }
     d.mask_words = std::max<size_t>(1, ((size_t(1) << p.batch_log2) + 31) / 32);
@@ -332,10 +347,8 @@ std::string upload_leaf(Plan& p, DeviceState& d, int leaf, std::vector<cd> data,
 // Capture one full launch group (slice id read from device memory) into a
 // graph: group-begin, max-slot reset, every slice-dependent step, slice sum.
 static std::string build_graph(Plan& p, DeviceState& d, void* ws, double* acc) {
-    if (d.gexec) {
-        (void)hipGraphExecDestroy(d.gexec);
-        d.gexec = nullptr;
-    }
+    std::string derr = drop_graph(d);
+    if (!derr.empty()) return derr;
     if (!d.cap_stream) TN_HIP(hipStreamCreateWithFlags(&d.cap_stream, hipStreamNonBlocking));
     const int storage = storage_of(p.opts.prec);
     hipStream_t c = d.cap_stream;
@@ -405,6 +418,8 @@ std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std
                 }
                 TN_HIP(launch_group_set(d.d_state, groups[i].slice_base >> p.batch_log2, s));
                 for (size_t k = i; k < j; ++k) TN_HIP(hipGraphLaunch(d.gexec, s));
+                if (!d.g_done) TN_HIP(hipEventCreateWithFlags(&d.g_done, hipEventDisableTiming));
+                TN_HIP(hipEventRecord(d.g_done, s));
                 d.graph_replays += j - i;
                 i = j;
             } else {
@@ -636,10 +651,8 @@ std::string autotune(Plan& p, DeviceState& d, void* ws, double* acc, const char*
     (void)hipEventDestroy(e1);
     if (!err.empty()) return err;
     // the captured graph used the old choices
-    if (d.gexec) {
-        (void)hipGraphExecDestroy(d.gexec);
-        d.gexec = nullptr;
-    }
+    err = drop_graph(d);
+    if (!err.empty()) return err;
     if (cache_path && !decided.empty()) {
         FILE* f = std::fopen(cache_path, "a");
         if (f) {
@@ -666,15 +679,12 @@ std::string set_step_kernel(Plan& p, DeviceState& d, int step, int kernel, int t
     if (kernel != K_SPLITK) st.splitk_log = 0;
     st.kernel = kernel;
     st.tile = tile;
-    if (d.gexec) {   // the captured graph used the old choice
-        (void)hipGraphExecDestroy(d.gexec);
-        d.gexec = nullptr;
-    }
-    return "";
+    return drop_graph(d);   // the captured graph used the old choice
 }
 
 void release(DeviceState& d) {
-    if (d.gexec) (void)hipGraphExecDestroy(d.gexec);
+    (void)drop_graph(d);
+    if (d.g_done) (void)hipEventDestroy(d.g_done);
     if (d.cap_stream) (void)hipStreamDestroy(d.cap_stream);
     if (d.d_state) (void)hipFree(d.d_state);
     for (int set = 0; set < 2; ++set)

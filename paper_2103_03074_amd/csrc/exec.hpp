@@ -33,6 +33,7 @@ struct DeviceState {
     GroupState* d_state = nullptr;     // graph replays: current launch group
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
     hipGraphExec_t gexec = nullptr;    // one launch group, replayed
+    hipEvent_t g_done = nullptr;       // recorded after the last replays of gexec
     void* g_ws = nullptr;              // buffers the graph was captured with
     double* g_acc = nullptr;
     uint64_t graph_replays = 0;        // statistics

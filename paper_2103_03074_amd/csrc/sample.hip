@@ -125,33 +125,41 @@ uint64_t sample_workspace_elems(uint64_t n) {
 hipError_t launch_sample(const double* amps, uint64_t n, const double* u, uint64_t n_samples, uint64_t* out,
                          double* ws, hipStream_t s) {
     if (n == 0) return hipErrorInvalidValue;
-    // level 0: the cdf itself; level l + 1: the block sums of level l
-    std::vector<std::pair<double*, uint64_t>> lv;
+    // level 0: the cdf itself; level l + 1: the block sums of level l (each
+    // level is 2^10 times shorter, so 8 levels cover n < 2^70; no host
+    // allocation)
+    constexpr int kMaxLevels = 8;
+    double* lv_ptr[kMaxLevels];
+    uint64_t lv_len[kMaxLevels];
+    int n_lv = 0;
     double* p = ws;
-    lv.push_back({p, n});
+    lv_ptr[n_lv] = p;
+    lv_len[n_lv++] = n;
     p += n;
     for (uint64_t m = blocks_for(n); ; m = blocks_for(m)) {
-        lv.push_back({p, m});
+        if (n_lv == kMaxLevels) return hipErrorInvalidValue;
+        lv_ptr[n_lv] = p;
+        lv_len[n_lv++] = m;
         p += m;
         if (m <= 1) break;
     }
     hipLaunchKernelGGL(k_prob_scan, dim3((unsigned)blocks_for(n)), dim3(kScanThreads), 0, s,
-                       reinterpret_cast<const double2*>(amps), n, lv[0].first, lv[1].first);
+                       reinterpret_cast<const double2*>(amps), n, lv_ptr[0], lv_ptr[1]);
     hipError_t e = hipGetLastError();
-    for (size_t l = 1; e == hipSuccess && l + 1 < lv.size(); ++l) {
-        hipLaunchKernelGGL(k_scan, dim3((unsigned)blocks_for(lv[l].second)), dim3(kScanThreads), 0, s, lv[l].first,
-                           lv[l].second, lv[l + 1].first);
+    for (int l = 1; e == hipSuccess && l + 1 < n_lv; ++l) {
+        hipLaunchKernelGGL(k_scan, dim3((unsigned)blocks_for(lv_len[l])), dim3(kScanThreads), 0, s, lv_ptr[l],
+                           lv_len[l], lv_ptr[l + 1]);
         e = hipGetLastError();
     }
-    for (size_t l = lv.size() - 1; e == hipSuccess && l-- > 0;) {
-        if (lv[l].second <= (uint64_t)kScanBlock) continue;   // one block: nothing to add
-        hipLaunchKernelGGL(k_add_offsets, dim3((unsigned)blocks_for(lv[l].second)), dim3(kScanThreads), 0, s,
-                           lv[l].first, lv[l].second, lv[l + 1].first);
+    for (int l = n_lv - 1; e == hipSuccess && l-- > 0;) {
+        if (lv_len[l] <= (uint64_t)kScanBlock) continue;   // one block: nothing to add
+        hipLaunchKernelGGL(k_add_offsets, dim3((unsigned)blocks_for(lv_len[l])), dim3(kScanThreads), 0, s,
+                           lv_ptr[l], lv_len[l], lv_ptr[l + 1]);
         e = hipGetLastError();
     }
     if (e != hipSuccess || n_samples == 0) return e;
     const uint64_t sb = std::min<uint64_t>((n_samples + 255) / 256, 1u << 20);   // grid-stride beyond that
-    hipLaunchKernelGGL(k_search, dim3((unsigned)sb), dim3(256), 0, s, lv[0].first, n, u, n_samples, out);
+    hipLaunchKernelGGL(k_search, dim3((unsigned)sb), dim3(256), 0, s, lv_ptr[0], n, u, n_samples, out);
     return hipGetLastError();
 }
 

@@ -67,7 +67,7 @@ class PlanStats(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_uint64), ("tail_workspace_bytes", ctypes.c_uint64),
                 ("n_dense_steps", ctypes.c_int32), ("n_small_steps", ctypes.c_int32),
                 ("cost_model_used", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
-                ("predicted_ms", ctypes.c_double)]
+                ("predicted_ms", ctypes.c_double), ("graph_replays", ctypes.c_uint64)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -215,6 +215,16 @@ def test_xeb_identities():
     assert np.isclose(top1, 2.0 ** n * p.max() - 1)
 
 
+def test_error_measures_hand_worked():
+    """Norm-wise and max-over-rms error on a hand-worked pair: ref = (3, 4i),
+    x = ref + (0, 1): ||x - ref|| = 1, ||ref|| = 5, rms(ref) = sqrt(25/2)."""
+    ref = np.array([3.0, 4.0j])
+    x = ref + np.array([0.0, 1.0])
+    assert stats.norm_rel_error(x, ref) == pytest.approx(0.2, rel=1e-15)
+    assert stats.max_err_over_rms(x, ref) == pytest.approx(1.0 / np.sqrt(12.5), rel=1e-15)
+    assert stats.max_err_over_rms(ref, ref) == 0.0
+
+
 def test_conditional_samples_inverse_transform():
     """Pins for inverse-transform sampling: a hand-worked case, the empirical
     law on an evenly spaced grid of uniforms (exact counts: grid points fall
