@@ -66,7 +66,7 @@ def kernel_table(profile):
     return agg
 
 
-def roofline_record(profile, prec, workload):
+def roofline_record(profile, prec, workload, cmacs_per_group):
     """Roofline record of the device function with the largest GPU time in
     the events pass: algorithmic flops (or bytes) per launch over its average
     launch duration, against the MFMA peak of the form (or HBM)."""
@@ -84,7 +84,7 @@ def roofline_record(profile, prec, workload):
     else:
         ach = a["bytes"] / n / avg_s / 1e9
         rec = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS}
-    rec["traffic"] = measured_traffic(workload, prec, name)
+    rec["traffic"] = measured_traffic(workload, prec, name, cmacs_per_group)
     rec.update({"kernel": name, "launches": a["launches"], "avg_launch_us": avg_s * 1e6,
                 "algorithmic_flops_per_launch": a["flops"] / n, "algorithmic_bytes_per_launch": a["bytes"] / n,
                 "arithmetic_intensity": ai,
@@ -119,11 +119,12 @@ def tree_roofline_fraction(profile, prec):
     return t_min / t_meas if t_meas > 0 else None
 
 
-def measured_traffic(workload, prec, kernel):
+def measured_traffic(workload, prec, kernel, cmacs_per_group):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary of this workload and form (FETCH_SIZE + WRITE_SIZE, calibrated
-    against a plain copy), or None when there is none or the kernel source
-    has changed since the counters were taken."""
+    against a plain copy), or None when there is none, the kernel source has
+    changed since the counters were taken, or the plan differs (its complex
+    multiply-adds per launch group are recorded with the counters)."""
     import hashlib
     suffix = "" if prec == "c64" else f"_{prec}"
     path = os.path.join(ROOT, "profiles", f"{workload}{suffix}_hbm_traffic.json")
@@ -134,6 +135,8 @@ def measured_traffic(workload, prec, kernel):
     with open(os.path.join(ROOT, "paper_2103_03074_amd", "csrc", "kernels.hip"), "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     if rec.get("kernels_source_sha256") != sha or kernel not in rec.get("kernels", {}):
+        return None
+    if rec.get("plan_cmacs_per_launch_group") != cmacs_per_group:
         return None
     return rec["kernels"][kernel]["hbm_bytes_per_launch"]
 
@@ -162,7 +165,7 @@ def cpu_baseline(w, plan, budget_s=20.0):
         t_all += time.perf_counter() - t0
         macs_all += macs
         done += 1
-        if t_all > budget_s or done >= min(n_slices, 64):
+        if t_all > budget_s or done >= min(n_slices, 1024):
             break
     t_slice = t_all / done
     amps = 2 ** len(w["open_q"])
@@ -325,7 +328,7 @@ def main():
         s = r["stats"]
         tflops = 8.0 * r["cmacs_step"] / r["sec_step"] / 1e12
         proj_job = r["sec_step"] / r["groups_per_step"] * r["n_groups"] + r["t_amp"]
-        roof, table = roofline_record(r["prof"], prec, args.workload)
+        roof, table = roofline_record(r["prof"], prec, args.workload, s["cmacs_per_batch"])
         d = {"ms_per_step": r["sec_step"] * 1e3, "TFLOP/s": tflops,
              "pct_of_form_mfma_peak": 100.0 * tflops / PEAK_TFLOPS[prec],
              "projected_seconds_per_job": proj_job,
@@ -334,6 +337,7 @@ def main():
              "kernels": table, "plan_seconds": r["t_plan"], "autotune_seconds": r["t_tune"],
              "autotuned_shapes": r["n_tuned"],
              "complex_macs_per_step": r["cmacs_step"],
+             "complex_macs_per_launch_group": s["cmacs_per_batch"],
              "complex_macs_per_slice_unmerged_tree": s["cmacs_per_slice_unmerged"],
              "complex_macs_slice_invariant_once": s["cmacs_invariant"]}
         if prec in ("split_fp16", "bf16"):

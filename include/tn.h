@@ -118,6 +118,14 @@ typedef struct {
     uint64_t seed;
     int64_t max_workspace_bytes;  /* cap for the per-launch workspace (0 = 32 GiB) */
     const struct tn_mlp_s* model; /* trained step-time model for cost_model = 1 (NULL = FLOP model) */
+    int32_t slicing;         /* planner-chosen slicing (appendix A, "Dynamic slicing"):
+                                2 = dynamic: edges are sliced one at a time, each the
+                                greedy choice on the current tree, and the tree is
+                                re-tuned by subtree reconfiguration after every sliced
+                                edge; 1 = one-shot: greedy slicing of the whole set on
+                                the unsliced tree, then one re-tune and a top-up;
+                                0 = both, per candidate tree, keeping the one with less
+                                total work over all slices */
 } tn_plan_opts;
 
 typedef struct {
@@ -143,7 +151,8 @@ typedef struct {
                                      outside its training support (FLOP count used) */
     int32_t n_candidates;         /* candidate trees/slicings ranked */
     double predicted_ms;          /* learned model's predicted time of the whole job (0 if unused) */
-    uint64_t graph_replays;       /* launch groups replayed from a captured graph on this plan so far */
+    uint64_t graph_replays;       /* launch groups replayed from captured graphs on this plan so far */
+    uint64_t graph_launches;      /* graph launches that replayed them (up to 16 groups per launch) */
 } tn_plan_stats;
 
 typedef struct {

@@ -112,6 +112,7 @@ tn_status tn_plan_stats_get(tn_plan_t p, tn_plan_stats* out) {
     if (!p || !out) return fail(TN_EINVAL, "NULL argument");
     *out = p->plan.stats;
     out->graph_replays = p->dev.graph_replays;
+    out->graph_launches = p->dev.graph_launches;
     return TN_OK;
 }
 

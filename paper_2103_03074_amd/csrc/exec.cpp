@@ -240,13 +240,19 @@ std::string profile_harvest_set(DeviceState& d, int set) {
 
 // Destroy the captured graph once every replay queued from it has finished:
 // its kernel nodes' argument buffers belong to the executable graph.
-static std::string drop_graph(DeviceState& d) {
-    if (!d.gexec) return "";
+static std::string drop_graph(DeviceState& d, int which) {
+    if (!d.gexec[which]) return "";
     hipError_t e = d.g_done ? hipEventSynchronize(d.g_done) : hipSuccess;
-    (void)hipGraphExecDestroy(d.gexec);
-    d.gexec = nullptr;
+    (void)hipGraphExecDestroy(d.gexec[which]);
+    d.gexec[which] = nullptr;
     if (e != hipSuccess) return std::string("hipEventSynchronize: ") + hipGetErrorString(e);
     return "";
+}
+
+static std::string drop_graphs(DeviceState& d) {
+    std::string e = drop_graph(d, 0);
+    std::string e1 = drop_graph(d, 1);
+    return e.empty() ? e1 : e;
 }
 
 std::string profile_harvest(DeviceState& d) {
@@ -344,10 +350,23 @@ std::string upload_leaf(Plan& p, DeviceState& d, int leaf, std::vector<cd> data,
     return "";
 }
 
-// Capture one full launch group (slice id read from device memory) into a
-// graph: group-begin, max-slot reset, every slice-dependent step, slice sum.
-static std::string build_graph(Plan& p, DeviceState& d, void* ws, double* acc) {
-    std::string derr = drop_graph(d);
+// Launch groups captured in one graph: enough to cover a bench step of 4096
+// slices at 2^8 slices per group, with at most about 4096 kernel nodes.
+constexpr int kMaxGraphGroups = 16;
+constexpr int kMaxGraphNodes = 4096;
+
+static int many_groups(const Plan& p) {
+    const int per_group = (int)p.steps.size() - p.n_invariant_steps + 3;
+    int g = 1;
+    while (g * 2 <= kMaxGraphGroups && g * 2 * per_group <= kMaxGraphNodes) g *= 2;
+    return g;
+}
+
+// Capture n_groups full launch groups (slice id read from device memory)
+// into one graph: per group, group-begin (advances the group index), max-slot
+// reset, every slice-dependent step, slice sum.
+static std::string build_graph(Plan& p, DeviceState& d, void* ws, double* acc, int which, int n_groups) {
+    std::string derr = drop_graph(d, which);
     if (!derr.empty()) return derr;
     if (!d.cap_stream) TN_HIP(hipStreamCreateWithFlags(&d.cap_stream, hipStreamNonBlocking));
     const int storage = storage_of(p.opts.prec);
@@ -355,51 +374,56 @@ static std::string build_graph(Plan& p, DeviceState& d, void* ws, double* acc) {
     const uint64_t* dsl = &d.d_state->slice_base;
     TN_HIP(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
     std::string err;
-    hipError_t e = launch_group_begin(d.d_state, p.batch_log2, c);
-    if (e == hipSuccess && d.d_max)
-        e = launch_fill(d.d_max + p.n_static_slots, (uint64_t)(p.tree.n_nodes() - p.n_static_slots), c);
-    if (e != hipSuccess) err = std::string("graph: ") + hipGetErrorString(e);
-    for (const Step& st : p.steps) {
-        if (!err.empty()) break;
-        if (st.invariant) continue;
-        void* A = node_ptr(p, d, ws, st.a_node, 0);
-        void* B = node_ptr(p, d, ws, st.b_node, 0);
-        void* C = (unsigned char*)ws + st.c_off * (uint64_t)p.esize;
-        err = launch_step(p, d, st, A, B, C, ws, c, nullptr, dsl);
-    }
-    if (err.empty()) {
-        const int root = p.tree.root();
-        uint8_t bit[8], pos[8];
-        const int rn = leaf_select(p, root, bit, pos);
-        e = launch_slice_sum(storage, node_ptr(p, d, ws, root, 0), acc, p.root_log2, p.batch_log2, nullptr, 0,
-                             1ull << p.batch_log2, c, rn ? dsl : nullptr, bit, pos, rn);
-        if (e != hipSuccess) err = std::string("graph slice sum: ") + hipGetErrorString(e);
+    for (int gi = 0; gi < n_groups && err.empty(); ++gi) {
+        hipError_t e = launch_group_begin(d.d_state, p.batch_log2, c);
+        if (e == hipSuccess && d.d_max)
+            e = launch_fill(d.d_max + p.n_static_slots, (uint64_t)(p.tree.n_nodes() - p.n_static_slots), c);
+        if (e != hipSuccess) err = std::string("graph: ") + hipGetErrorString(e);
+        for (const Step& st : p.steps) {
+            if (!err.empty()) break;
+            if (st.invariant) continue;
+            void* A = node_ptr(p, d, ws, st.a_node, 0);
+            void* B = node_ptr(p, d, ws, st.b_node, 0);
+            void* C = (unsigned char*)ws + st.c_off * (uint64_t)p.esize;
+            err = launch_step(p, d, st, A, B, C, ws, c, nullptr, dsl);
+        }
+        if (err.empty()) {
+            const int root = p.tree.root();
+            uint8_t bit[8], pos[8];
+            const int rn = leaf_select(p, root, bit, pos);
+            e = launch_slice_sum(storage, node_ptr(p, d, ws, root, 0), acc, p.root_log2, p.batch_log2, nullptr, 0,
+                                 1ull << p.batch_log2, c, rn ? dsl : nullptr, bit, pos, rn);
+            if (e != hipSuccess) err = std::string("graph slice sum: ") + hipGetErrorString(e);
+        }
     }
     hipGraph_t graph = nullptr;
     hipError_t ee = hipStreamEndCapture(c, &graph);
     if (err.empty() && ee != hipSuccess) err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ee);
     if (err.empty()) {
-        ee = hipGraphInstantiate(&d.gexec, graph, nullptr, nullptr, 0);
+        ee = hipGraphInstantiate(&d.gexec[which], graph, nullptr, nullptr, 0);
         if (ee != hipSuccess) err = std::string("hipGraphInstantiate: ") + hipGetErrorString(ee);
     }
     if (graph) (void)hipGraphDestroy(graph);
     if (err.empty()) {
-        d.g_ws = ws;
-        d.g_acc = acc;
+        d.g_ws[which] = ws;
+        d.g_acc[which] = acc;
+        if (which == 1) d.g_many = n_groups;
     } else {
-        d.gexec = nullptr;
+        d.gexec[which] = nullptr;
     }
     return err;
 }
 
 std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std::vector<Group>& groups,
                        hipStream_t s) {
-    // full, consecutive launch groups are replayed from one captured graph
-    // unless per-step timing is on (it needs eager launches)
+    // runs of full, consecutive launch groups are replayed from captured
+    // graphs (several groups per launch where the run is long enough) unless
+    // per-step timing is on (it needs eager launches)
     static const bool no_graph = std::getenv("TN_NO_GRAPH") != nullptr;
     if (!d.prof.on && !no_graph && d.d_state && groups.size() >= 2) {
         size_t i = 0;
         std::vector<Group> eager;
+        const int many = many_groups(p);
         while (i < groups.size()) {
             size_t j = i;
             const uint64_t B = 1ull << p.batch_log2;
@@ -412,15 +436,24 @@ std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std
                     if (!e.empty()) return e;
                     eager.clear();
                 }
-                if (!d.gexec || d.g_ws != ws || d.g_acc != acc) {
-                    std::string e = build_graph(p, d, ws, acc);
+                const size_t n = j - i;
+                const size_t n_many = many > 1 ? n / (size_t)many : 0;
+                const size_t n_one = n - n_many * (size_t)many;
+                if (n_many && (!d.gexec[1] || d.g_ws[1] != ws || d.g_acc[1] != acc || d.g_many != many)) {
+                    std::string e = build_graph(p, d, ws, acc, 1, many);
+                    if (!e.empty()) return e;
+                }
+                if (n_one && (!d.gexec[0] || d.g_ws[0] != ws || d.g_acc[0] != acc)) {
+                    std::string e = build_graph(p, d, ws, acc, 0, 1);
                     if (!e.empty()) return e;
                 }
                 TN_HIP(launch_group_set(d.d_state, groups[i].slice_base >> p.batch_log2, s));
-                for (size_t k = i; k < j; ++k) TN_HIP(hipGraphLaunch(d.gexec, s));
+                for (size_t k = 0; k < n_many; ++k) TN_HIP(hipGraphLaunch(d.gexec[1], s));
+                for (size_t k = 0; k < n_one; ++k) TN_HIP(hipGraphLaunch(d.gexec[0], s));
                 if (!d.g_done) TN_HIP(hipEventCreateWithFlags(&d.g_done, hipEventDisableTiming));
                 TN_HIP(hipEventRecord(d.g_done, s));
-                d.graph_replays += j - i;
+                d.graph_replays += n;
+                d.graph_launches += n_many + n_one;
                 i = j;
             } else {
                 eager.push_back(groups[i]);
@@ -650,8 +683,8 @@ std::string autotune(Plan& p, DeviceState& d, void* ws, double* acc, const char*
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (!err.empty()) return err;
-    // the captured graph used the old choices
-    err = drop_graph(d);
+    // the captured graphs used the old choices
+    err = drop_graphs(d);
     if (!err.empty()) return err;
     if (cache_path && !decided.empty()) {
         FILE* f = std::fopen(cache_path, "a");
@@ -679,11 +712,11 @@ std::string set_step_kernel(Plan& p, DeviceState& d, int step, int kernel, int t
     if (kernel != K_SPLITK) st.splitk_log = 0;
     st.kernel = kernel;
     st.tile = tile;
-    return drop_graph(d);   // the captured graph used the old choice
+    return drop_graphs(d);   // the captured graphs used the old choice
 }
 
 void release(DeviceState& d) {
-    (void)drop_graph(d);
+    (void)drop_graphs(d);
     if (d.g_done) (void)hipEventDestroy(d.g_done);
     if (d.cap_stream) (void)hipStreamDestroy(d.cap_stream);
     if (d.d_state) (void)hipFree(d.d_state);

@@ -32,11 +32,15 @@ struct DeviceState {
     float* d_max = nullptr;       // per-tensor max |re|,|im| (low-precision MFMA scaling)
     GroupState* d_state = nullptr;     // graph replays: current launch group
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
-    hipGraphExec_t gexec = nullptr;    // one launch group, replayed
-    hipEvent_t g_done = nullptr;       // recorded after the last replays of gexec
-    void* g_ws = nullptr;              // buffers the graph was captured with
-    double* g_acc = nullptr;
-    uint64_t graph_replays = 0;        // statistics
+    // captured graphs: gexec[0] runs one launch group, gexec[1] g_many
+    // consecutive groups (the group index advances on the device)
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int g_many = 0;
+    hipEvent_t g_done = nullptr;       // recorded after the last replays
+    void* g_ws[2] = {nullptr, nullptr};    // buffers each graph was captured with
+    double* g_acc[2] = {nullptr, nullptr};
+    uint64_t graph_replays = 0;        // statistics: launch groups replayed from graphs
+    uint64_t graph_launches = 0;       // and graph launches
     Profiler prof;
 };
 

@@ -57,6 +57,8 @@ tn_plan_opts default_opts() {
     o.cost_model = 0;
     o.seed = 0;
     o.max_workspace_bytes = 0;
+    o.model = nullptr;
+    o.slicing = 0;
     return o;
 }
 
@@ -206,6 +208,35 @@ SliceCost slice_cost_tl(const TreeLegs& tl, const Tree& t, const std::vector<cha
 // Greedy slicing: repeatedly fix the edge whose removal gives the lowest total
 // work, among the legs of the largest intermediates, until the memory target
 // and the requested count are both met.
+// One greedy slicing choice on the current tree: among the legs of the
+// largest tensors (those at the largest size while over the target, else
+// within a factor 2 of it), the edge whose slicing gives the lowest total
+// cost over all slices; -1 if there is none.
+static int greedy_slice_step(const Network& net, const Tree& t, const TreeLegs& tl, std::vector<char>& in_s,
+                             const std::vector<char>& is_open, int k, bool over) {
+    const SliceCost cur = slice_cost_tl(tl, t, in_s);
+    const int thresh = over ? cur.max_log2 : std::max(0, cur.max_log2 - 1);
+    std::set<int> cands;
+    for (int c = t.n_leaves; c < t.n_nodes(); ++c) {
+        if (count_not_in(tl.node[c], in_s) < thresh) continue;
+        for (int e : tl.node[c])
+            if (!in_s[e] && !is_open[e]) cands.insert(e);
+    }
+    int best = -1;
+    double best_cost = 0;
+    for (int e : cands) {
+        in_s[e] = 1;
+        SliceCost nc = slice_cost_tl(tl, t, in_s);
+        in_s[e] = 0;
+        double tot = nc.total(k + 1);
+        if (best < 0 || tot < best_cost * (1 - 1e-12)) {
+            best = e;
+            best_cost = tot;
+        }
+    }
+    return best;
+}
+
 std::vector<int> greedy_slice(const Network& net, const Tree& t, const TreeLegs& tl, int target,
                               int n_force, std::vector<int> sliced) {
     const int E = (int)net.edge_name.size();
@@ -213,33 +244,42 @@ std::vector<int> greedy_slice(const Network& net, const Tree& t, const TreeLegs&
     for (int e : net.open_edges) is_open[e] = 1;
     for (int e : sliced) in_s[e] = 1;
     while (true) {
-        SliceCost cur = slice_cost_tl(tl, t, in_s);
         const int k = (int)sliced.size();
-        const bool over = cur.max_log2 > target;
+        const bool over = slice_cost_tl(tl, t, in_s).max_log2 > target;
         if (!over && k >= n_force) break;
-        const int thresh = over ? cur.max_log2 : std::max(0, cur.max_log2 - 1);
-        std::set<int> cands;
-        for (int c = t.n_leaves; c < t.n_nodes(); ++c) {
-            if (count_not_in(tl.node[c], in_s) < thresh) continue;
-            for (int e : tl.node[c])
-                if (!in_s[e] && !is_open[e]) cands.insert(e);
-        }
-        if (cands.empty() || k >= 62) break;
-        int best = -1;
-        double best_cost = 0;
-        for (int e : cands) {
-            in_s[e] = 1;
-            SliceCost nc = slice_cost_tl(tl, t, in_s);
-            in_s[e] = 0;
-            double tot = nc.total(k + 1);
-            if (best < 0 || tot < best_cost * (1 - 1e-12)) {
-                best = e;
-                best_cost = tot;
-            }
-        }
+        if (k >= 62) break;
+        const int best = greedy_slice_step(net, t, tl, in_s, is_open, k, over);
+        if (best < 0) break;
         in_s[best] = 1;
         sliced.push_back(best);
     }
+    return sliced;
+}
+
+// Dynamic slicing (appendix A, "Dynamic slicing"): edges are sliced one at a
+// time, each the greedy choice on the current tree, and after every sliced
+// edge the tree is fine-tuned by subtree reconfiguration with the sliced legs
+// removed (a few passes; a full re-tune at the end).  Stops when the largest
+// intermediate meets the target and at least n_force edges are sliced.
+std::vector<int> dynamic_slice(const Network& net, const std::vector<Legs>& leaf_legs, Tree& t, int target,
+                               int n_force) {
+    const int E = (int)net.edge_name.size();
+    std::vector<int> sliced;
+    std::vector<char> in_s(E, 0), is_open(E, 0);
+    for (int e : net.open_edges) is_open[e] = 1;
+    TreeLegs tl = tree_legs(net, t);
+    while (true) {
+        const int k = (int)sliced.size();
+        const bool over = slice_cost_tl(tl, t, in_s).max_log2 > target;
+        if ((!over && k >= n_force) || k >= 62) break;
+        const int best = greedy_slice_step(net, t, tl, in_s, is_open, k, over);
+        if (best < 0) break;
+        in_s[best] = 1;
+        sliced.push_back(best);
+        t = reconfigure(leaf_legs, t, in_s, target, 8, 2);
+        tl = tree_legs(net, t);
+    }
+    t = reconfigure(leaf_legs, t, in_s, target, 8, 16);
     return sliced;
 }
 
@@ -770,11 +810,19 @@ static std::string plan_network(Plan& out, const tn_tree* tree, const std::vecto
                 for (int e : user_sliced) in_s[e] = 1;
             t = reconfigure(leaf_legs, t, in_s, fixed_slicing ? opts.max_log2_size : 64, 8, 16);
         }
+        // dynamic slicing (re-tune after every sliced edge) on a copy of the
+        // tree; compared below with one-shot slicing plus one re-tune
+        Tree t_dyn = t;
+        std::vector<int> s_dyn;
+        const bool try_dyn = !tree && !fixed_slicing && opts.slicing != 1;
+        const bool try_one = tree || fixed_slicing || opts.slicing != 2;
+        if (try_dyn) s_dyn = dynamic_slice(net, leaf_legs, t_dyn, opts.max_log2_size, n_force);
         TreeLegs tl = tree_legs(net, t);
         std::vector<int> s = fixed_slicing ? user_sliced
-                                           : greedy_slice(net, t, tl, opts.max_log2_size, n_force, {});
+                                           : (try_one ? greedy_slice(net, t, tl, opts.max_log2_size, n_force, {})
+                                                      : std::vector<int>());
         for (int e : s) in_s[e] = 1;
-        if (!tree && !fixed_slicing && !s.empty()) {
+        if (!tree && !fixed_slicing && try_one && !s.empty()) {
             // re-tune the tree for one slice, then top up the slicing if needed
             Tree t2 = reconfigure(leaf_legs, t, in_s, opts.max_log2_size, 8, 16);
             TreeLegs tl2 = tree_legs(net, t2);
@@ -787,6 +835,19 @@ static std::string plan_network(Plan& out, const tn_tree* tree, const std::vecto
                 tl = tl2;
                 s = s2;
                 in_s = in2;
+            }
+        }
+        if (try_dyn) {
+            TreeLegs tld = tree_legs(net, t_dyn);
+            std::vector<char> ind(E, 0);
+            for (int e : s_dyn) ind[e] = 1;
+            const SliceCost scd = slice_cost_tl(tld, t_dyn, ind);
+            if (!try_one || (scd.max_log2 <= opts.max_log2_size &&
+                             scd.total((int)s_dyn.size()) < slice_cost_tl(tl, t, in_s).total((int)s.size()))) {
+                t = t_dyn;
+                tl = tld;
+                s = s_dyn;
+                in_s = ind;
             }
         }
         SliceCost sc = slice_cost_tl(tl, t, in_s);

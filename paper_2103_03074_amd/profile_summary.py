@@ -141,14 +141,17 @@ def counter_table(directory, copy_kib=None):
     return means, count, factors, counters
 
 
-def bench_alg_bytes(path):
+def bench_record(path):
+    """Algorithmic bytes per launch of each kernel and the plan's complex
+    multiply-adds per launch group, from the bench's JSON line."""
     if not path:
-        return {}
+        return {}, None
     with open(path) as f:
         line = [ln for ln in f if ln.strip().startswith("{")][-1]
     rec = json.loads(line)
-    tab = rec.get("main", {}).get("kernels", {})
-    return {k: v.get("alg_bytes_per_launch") for k, v in tab.items()}
+    main = rec.get("main", {})
+    tab = main.get("kernels", {})
+    return {k: v.get("alg_bytes_per_launch") for k, v in tab.items()}, main.get("complex_macs_per_launch_group")
 
 
 def main():
@@ -184,13 +187,13 @@ def main():
     wr, _, wr_f, _ = counter_table(args.write, copy_kib)
     f_fac, f_raw = fe_f["FETCH_SIZE"]
     w_fac, w_raw = wr_f["WRITE_SIZE"]
-    alg = bench_alg_bytes(args.bench_json)
+    alg, plan_cmacs = bench_record(args.bench_json)
     sha = kernel_source_sha()
     if args.source_sha_file:
         with open(args.source_sha_file) as f:
             sha = f.read().split()[0]
     res = {"copy_mib": args.copy_mib, "fetch_factor": f_fac, "write_factor": w_fac,
-           "kernels_source_sha256": sha, "kernels": {}}
+           "kernels_source_sha256": sha, "plan_cmacs_per_launch_group": plan_cmacs, "kernels": {}}
     lines = [f"# HBM traffic per dispatch, timed steps only: {args.title}", ""] + cmd_lines
     lines += ["",
               f"Calibration: each of the two bracketing device copies of {args.copy_mib} MiB reads FETCH_SIZE "

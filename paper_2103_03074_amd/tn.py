@@ -51,7 +51,7 @@ class PlanOpts(ctypes.Structure):
                 ("branch_merge", ctypes.c_int32), ("bighead", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("cost_model", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("max_workspace_bytes", ctypes.c_int64),
-                ("model", ctypes.c_void_p)]
+                ("model", ctypes.c_void_p), ("slicing", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -67,7 +67,8 @@ class PlanStats(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_uint64), ("tail_workspace_bytes", ctypes.c_uint64),
                 ("n_dense_steps", ctypes.c_int32), ("n_small_steps", ctypes.c_int32),
                 ("cost_model_used", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
-                ("predicted_ms", ctypes.c_double), ("graph_replays", ctypes.c_uint64)]
+                ("predicted_ms", ctypes.c_double), ("graph_replays", ctypes.c_uint64),
+                ("graph_launches", ctypes.c_uint64)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -185,10 +186,10 @@ def _circuit_c(circuit):
 
 
 def plan_options(prec="c64", max_log2_size=30, n_slice_edges=-1, batch_log2=-1, branch_merge=0,
-                 bighead=0, restarts=8, cost_model=0, seed=0, max_workspace_bytes=0, model=None):
+                 bighead=0, restarts=8, cost_model=0, seed=0, max_workspace_bytes=0, model=None, slicing=0):
     return PlanOpts(PRECISIONS[prec] if isinstance(prec, str) else int(prec), max_log2_size, n_slice_edges,
                     batch_log2, branch_merge, bighead, restarts, cost_model, seed, max_workspace_bytes,
-                    model.handle if model is not None else None)
+                    model.handle if model is not None else None, slicing)
 
 
 def choose_open_qubits(circuit, n_open, **opts):
