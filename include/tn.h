@@ -262,6 +262,23 @@ size_t tn_sample_workspace_bytes(int32_t n_open);
 tn_status tn_sample(const double* d_amps, int32_t n_open, const double* d_uniform, uint64_t n_samples,
                     uint64_t* d_out, void* d_workspace, size_t ws_bytes, void* hip_stream);
 
+/* tn_sample without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, same
+ * kernels and bitwise the same samples as tn_sample.  The workspace is a
+ * file-scope device array of 8.0 MiB (2^20 probabilities and their scan
+ * levels) that every GPU the library runs on holds until the process ends;
+ * its address on a device is looked up once, at the first call on that
+ * device.  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU (other streams, other threads) race and must be serialised by
+ * the caller.  Nothing in the array needs clearing between calls (every
+ * element read is first written by the same call).  Asynchronous on
+ * hip_stream.  TN_EINVAL for NULL pointers (d_uniform and d_out may be NULL
+ * when n_samples is 0) or n_open outside [0, 20]; TN_EDEVICE for launch
+ * errors. */
+tn_status tn_sample_noalloc(const double* d_amps, int32_t n_open, const double* d_uniform, uint64_t n_samples,
+                            uint64_t* d_out, void* hip_stream);
+
 /* Per-step timing of the slice-dependent steps, for measurement and for the
  * learned step-time model.  While enabled, tn_contract_slices records HIP
  * events around every step it launches (two event sets used alternately, so

@@ -274,6 +274,18 @@ tn_status tn_sample(const double* d_amps, int32_t n_open, const double* d_unifor
     return TN_OK;
 }
 
+tn_status tn_sample_noalloc(const double* d_amps, int32_t n_open, const double* d_uniform, uint64_t n_samples,
+                            uint64_t* d_out, void* hip_stream) {
+    if (!d_amps || (n_samples > 0 && (!d_uniform || !d_out))) return fail(TN_EINVAL, "NULL argument");
+    if (n_open < 0 || n_open > tn::kStaticSampleMaxOpen)
+        return fail(TN_EINVAL, "n_open above the allocation-free limit of " +
+                                   std::to_string(tn::kStaticSampleMaxOpen));
+    hipError_t e = tn::launch_sample_static(d_amps, 1ull << n_open, d_uniform, n_samples, d_out,
+                                            reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(TN_EDEVICE, std::string("sample: ") + hipGetErrorString(e));
+    return TN_OK;
+}
+
 tn_status tn_xeb(const double* d_amps, int32_t n_open, int32_t n_qubits, double weight, const int64_t* ks,
                  int32_t n_ks, double* h_topk, tn_xeb_result* out, void* hip_stream) {
     if (!d_amps || !out) return fail(TN_EINVAL, "NULL argument");

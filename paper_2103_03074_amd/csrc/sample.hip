@@ -9,6 +9,7 @@
 #include "sample.hpp"
 
 #include <algorithm>
+#include <mutex>
 
 namespace tn {
 
@@ -120,6 +121,50 @@ uint64_t sample_workspace_elems(uint64_t n) {
         if (m <= 1) break;
     }
     return total;
+}
+
+namespace {
+
+constexpr uint64_t static_elems(uint64_t n) {
+    uint64_t total = n;
+    for (uint64_t m = (n + kScanBlock - 1) / kScanBlock; ; m = (m + kScanBlock - 1) / kScanBlock) {
+        total += m;
+        if (m <= 1) break;
+    }
+    return total;
+}
+
+// Workspace of the allocation-free entry point: 2^20 probabilities and their
+// scan levels (8.0 MiB), one copy per GPU, held until the process ends.
+// Host code never uses this name as an address: each device's address comes
+// from hipGetSymbolAddress.
+__device__ __align__(256) double scratch[static_elems(1ull << kStaticSampleMaxOpen)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+hipError_t launch_sample_static(const double* amps, uint64_t n, const double* u, uint64_t n_samples, uint64_t* out,
+                                hipStream_t s) {
+    if (n == 0 || n > (1ull << kStaticSampleMaxOpen)) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    double* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {   // once per device, with that device current
+            void* ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            g_scratch_ptr[dev] = static_cast<double*>(ptr);
+        }
+        ws = g_scratch_ptr[dev];
+    }
+    return launch_sample(amps, n, u, n_samples, out, ws, s);
 }
 
 hipError_t launch_sample(const double* amps, uint64_t n, const double* u, uint64_t n_samples, uint64_t* out,

@@ -17,4 +17,11 @@ uint64_t sample_workspace_elems(uint64_t n);
 hipError_t launch_sample(const double* amps, uint64_t n, const double* u, uint64_t n_samples, uint64_t* out,
                          double* ws, hipStream_t s);
 
+// Same with the workspace in a file-scope device array (no allocation):
+// n <= 2^kStaticSampleMaxOpen.  Calls that overlap on one GPU share the
+// array and race.
+constexpr int kStaticSampleMaxOpen = 20;
+hipError_t launch_sample_static(const double* amps, uint64_t n, const double* u, uint64_t n_samples, uint64_t* out,
+                                hipStream_t s);
+
 }  // namespace tn

@@ -120,6 +120,7 @@ _SIGS = {
     "tn_plan_set_step_kernel": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "tn_sample_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "tn_sample": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P, ctypes.c_size_t, _P]),
+    "tn_sample_noalloc": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P]),
     "tn_plan_set_profiling": (ctypes.c_int, [_P, ctypes.c_int32]),
     "tn_plan_step_profile": (ctypes.c_int, [_P, ctypes.POINTER(StepProfile), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
@@ -416,6 +417,17 @@ def sample(amps, n_open, uniforms, out, ws, stream=None):
     _check(library().tn_sample(ctypes.c_void_p(amps.data_ptr()), int(n_open), ctypes.c_void_p(uniforms.data_ptr()),
                                n, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                                ws.numel() * ws.element_size(), _stream_ptr(stream)))
+
+
+def sample_noalloc(amps, n_open, uniforms, out, stream=None):
+    """tn_sample with the library's file-scope device workspace (no
+    allocation; n_open <= 20; overlapping calls on one GPU race)."""
+    n = int(uniforms.numel())
+    if int(out.numel()) != n:
+        raise ValueError("out and uniforms must have the same length")
+    _check(library().tn_sample_noalloc(ctypes.c_void_p(amps.data_ptr()), int(n_open),
+                                       ctypes.c_void_p(uniforms.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
+                                       _stream_ptr(stream)))
 
 
 def xeb(amps, n_open, n_qubits, weight=1.0, ks=(), stream=None):
