@@ -279,6 +279,35 @@ tn_status tn_sample(const double* d_amps, int32_t n_open, const double* d_unifor
 tn_status tn_sample_noalloc(const double* d_amps, int32_t n_open, const double* d_uniform, uint64_t n_samples,
                             uint64_t* d_out, void* hip_stream);
 
+/* Mixing the most probable computed bitstrings with random ones (section
+ * "Discussions", footnote: the k bitstrings of highest probability are mixed
+ * with many random bitstrings, which removes most of the correlation of the
+ * set while its XEB stays positive).  d_amps: 2^n_open complex128 amplitudes
+ * of the open qubits (first open qubit the most significant bit), open_q
+ * ascending; open_q and fixed_q together are the qubits 0..n_qubits-1, and
+ * fixed_bits (one byte per fixed qubit) is s1.  Writes d_out[0, k): the k
+ * indices of largest |A|^2 (computed as re*re + im*im, each product rounded;
+ * ties at the threshold go to the lower index), in increasing index order,
+ * as whole n-bit strings with qubit q at bit n_qubits-1-q; and
+ * d_out[k, k + n_random): the caller's uniform random 64-bit words
+ * d_random_words masked to n_qubits bits.  out receives P_top (sum of the
+ * selected probabilities, in a fixed order), F_top = 2^n / k * P_top - 1
+ * (the XEB of the top k alone) and F_mix_expected = (2^n P_top + n_random) /
+ * (k + n_random) - 1, the XEB of the whole set in expectation over the random
+ * strings (a uniform random string has expected 2^n P = 1).  Device buffers
+ * are caller-owned; d_workspace holds tn_mix_workspace_bytes(n_open) bytes.
+ * Synchronises the stream.  TN_EINVAL for NULL pointers, qubit lists that do
+ * not partition 0..n-1, n_qubits > 64, n_open > 34, k > 2^n_open or a small
+ * workspace. */
+typedef struct {
+    double P_top, F_top, F_mix_expected;
+} tn_mix_result;
+size_t tn_mix_workspace_bytes(int32_t n_open);
+tn_status tn_mix_topk(const double* d_amps, int32_t n_qubits, const int32_t* open_q, int32_t n_open,
+                      const int32_t* fixed_q, const uint8_t* fixed_bits, int32_t n_fixed, uint64_t k,
+                      const uint64_t* d_random_words, uint64_t n_random, uint64_t* d_out, void* d_workspace,
+                      size_t ws_bytes, tn_mix_result* out, void* hip_stream);
+
 /* Per-step timing of the slice-dependent steps, for measurement and for the
  * learned step-time model.  While enabled, tn_contract_slices records HIP
  * events around every step it launches (two event sets used alternately, so

@@ -96,3 +96,40 @@ def max_err_over_rms(x, ref):
     ref = np.asarray(ref)
     rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
     return float(np.max(np.abs(x - ref)) / rms)
+
+
+def full_bitstrings(s2_indices, n_qubits, open_q, fixed_q, fixed_bits):
+    """Whole n-bit strings (as integers, qubit q at bit n-1-q) of open-qubit
+    indices s2 (first open qubit the most significant bit of s2) with the
+    closed qubits at s1."""
+    n2 = len(open_q)
+    base = 0
+    for q, b in zip(fixed_q, fixed_bits):
+        base |= int(b) << (n_qubits - 1 - int(q))
+    out = []
+    for s2 in s2_indices:
+        v = base
+        for j, q in enumerate(open_q):
+            v |= ((int(s2) >> (n2 - 1 - j)) & 1) << (n_qubits - 1 - int(q))
+        out.append(v)
+    return out
+
+
+def mix_top_with_random(p, k, n_qubits, random_strings):
+    """Mixing the k most probable computed bitstrings with random ones
+    (section "Discussions", footnote on relaxing the correlation of the
+    samples): the top k indices of p (ties broken towards the lower index),
+    returned in increasing index order, the XEB of those k alone
+    F_top = 2^n / k * sum_top p - 1, and the expected XEB of the whole set of
+    N = k + R bitstrings when the R random bitstrings are uniform over all
+    2^n strings (their expected 2^n p is 1):
+    F_mix = (2^n * sum_top p + R) / N - 1 = k / N * F_top."""
+    p = np.asarray(p, dtype=np.float64)
+    order = np.lexsort((np.arange(p.size), -p))     # probability descending, then index ascending
+    top = np.sort(order[:k])
+    s = float(np.sum(p[top]))
+    r = len(random_strings)
+    n_all = k + r
+    f_top = (2.0 ** n_qubits) / k * s - 1.0 if k else 0.0
+    f_mix = ((2.0 ** n_qubits) * s + r) / n_all - 1.0 if n_all else 0.0
+    return top, s, f_top, f_mix

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "exec.hpp"
+#include "mix.hpp"
 #include "sample.hpp"
 #include "mlp.hpp"
 #include "plan.hpp"
@@ -283,6 +284,50 @@ tn_status tn_sample_noalloc(const double* d_amps, int32_t n_open, const double* 
     hipError_t e = tn::launch_sample_static(d_amps, 1ull << n_open, d_uniform, n_samples, d_out,
                                             reinterpret_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return fail(TN_EDEVICE, std::string("sample: ") + hipGetErrorString(e));
+    return TN_OK;
+}
+
+size_t tn_mix_workspace_bytes(int32_t n_open) {
+    if (n_open < 0 || n_open > 34) return 0;
+    return tn::mix_workspace_bytes(1ull << n_open);
+}
+
+tn_status tn_mix_topk(const double* d_amps, int32_t n_qubits, const int32_t* open_q, int32_t n_open,
+                      const int32_t* fixed_q, const uint8_t* fixed_bits, int32_t n_fixed, uint64_t k,
+                      const uint64_t* d_random_words, uint64_t n_random, uint64_t* d_out, void* d_workspace,
+                      size_t ws_bytes, tn_mix_result* out, void* hip_stream) {
+    if (!d_amps || !out || (n_open > 0 && !open_q) || (n_fixed > 0 && (!fixed_q || !fixed_bits)))
+        return fail(TN_EINVAL, "NULL argument");
+    if (n_open < 0 || n_open > 34 || n_fixed < 0 || n_qubits != n_open + n_fixed || n_qubits > 64)
+        return fail(TN_EINVAL, "bad sizes (n_qubits = n_open + n_fixed <= 64, n_open <= 34)");
+    const uint64_t L = 1ull << n_open;
+    if (k > L) return fail(TN_EINVAL, "k exceeds the number of computed amplitudes");
+    if ((k + n_random > 0 && !d_out) || (n_random > 0 && !d_random_words)) return fail(TN_EINVAL, "NULL buffer");
+    if (!d_workspace || ws_bytes < tn_mix_workspace_bytes(n_open))
+        return fail(TN_EINVAL, "workspace smaller than tn_mix_workspace_bytes");
+    tn::MixBits mb{};
+    std::vector<char> seen(n_qubits, 0);
+    for (int i = 0; i < n_open + n_fixed; ++i) {
+        const int q = i < n_open ? open_q[i] : fixed_q[i - n_open];
+        if (q < 0 || q >= n_qubits || seen[q]) return fail(TN_EINVAL, "open and fixed qubits must partition 0..n-1");
+        seen[q] = 1;
+    }
+    for (int j = 0; j < n_open; ++j) {
+        if (j && open_q[j] <= open_q[j - 1]) return fail(TN_EINVAL, "open qubits must be ascending");
+        mb.pos[j] = (uint8_t)(n_qubits - 1 - open_q[j]);
+    }
+    mb.n_open = n_open;
+    for (int i = 0; i < n_fixed; ++i)
+        if (fixed_bits[i]) mb.base |= 1ull << (n_qubits - 1 - fixed_q[i]);
+    double p_top = 0.0;
+    std::string err = tn::mix_topk(d_amps, L, k, mb, d_random_words, n_random, n_qubits, d_out, d_workspace,
+                                   reinterpret_cast<hipStream_t>(hip_stream), p_top);
+    if (!err.empty()) return fail(TN_EDEVICE, err);
+    const double two_n = std::ldexp(1.0, n_qubits);
+    out->P_top = p_top;
+    out->F_top = k ? two_n / (double)k * p_top - 1.0 : 0.0;
+    const double n_all = (double)k + (double)n_random;
+    out->F_mix_expected = n_all > 0 ? (two_n * p_top + (double)n_random) / n_all - 1.0 : 0.0;
     return TN_OK;
 }
 

@@ -116,16 +116,19 @@ def counter_table(directory, copy_kib=None):
     dispatches, the dispatch count, and (when copy_kib is given) the factor of
     each counter that makes the bracketing copies read copy_kib."""
     per = collections.defaultdict(dict)   # dispatch id -> counter -> value
-    name = {}
+    name, grid = {}, {}
     for r in read_csv(directory, "counter_collection.csv"):
         d = int(col(r, "Dispatch_Id"))
         c = col(r, "Counter_Name")
         per[d][c] = per[d].get(c, 0.0) + float(col(r, "Counter_Value"))
         name[d] = short_name(col(r, "Kernel_Name"))
+        grid[d] = int(col(r, "Grid_Size"))
     counters = sorted({c for v in per.values() for c in v})
-    first = counters[0]
-    ds = [(d, name[d], per[d]) for d in per]
-    inner, marks = bracketed(ds, lambda v: v.get(first, 0.0))
+    ds = [(d, name[d], (grid[d], per[d])) for d in per]
+    # the bracketing copies are the copy dispatches with the largest grids
+    inner, marks = bracketed(ds, lambda v: v[0])
+    inner = [(d, k, v[1]) for d, k, v in inner]
+    marks = [(d, k, v[1]) for d, k, v in marks]
     agg = collections.defaultdict(list)
     for _, k, v in inner:
         agg[k].append(v)

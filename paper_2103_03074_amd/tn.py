@@ -82,6 +82,10 @@ class XebResult(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class MixResult(ctypes.Structure):
+    _fields_ = [("P_top", ctypes.c_double), ("F_top", ctypes.c_double), ("F_mix_expected", ctypes.c_double)]
+
+
 class StepProfile(ctypes.Structure):
     _fields_ = [("m_log", ctypes.c_int32), ("n_log", ctypes.c_int32), ("k_log", ctypes.c_int32),
                 ("b_log", ctypes.c_int32), ("kernel", ctypes.c_int32), ("tile", ctypes.c_int32),
@@ -120,6 +124,11 @@ _SIGS = {
     "tn_plan_set_step_kernel": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "tn_sample_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "tn_sample": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P, ctypes.c_size_t, _P]),
+    "tn_mix_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "tn_mix_topk": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32,
+                                   ctypes.c_uint64, _P, ctypes.c_uint64, _P, _P, ctypes.c_size_t,
+                                   ctypes.POINTER(MixResult), _P]),
     "tn_sample_noalloc": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P]),
     "tn_plan_set_profiling": (ctypes.c_int, [_P, ctypes.c_int32]),
     "tn_plan_step_profile": (ctypes.c_int, [_P, ctypes.POINTER(StepProfile), ctypes.c_int32,
@@ -428,6 +437,30 @@ def sample_noalloc(amps, n_open, uniforms, out, stream=None):
     _check(library().tn_sample_noalloc(ctypes.c_void_p(amps.data_ptr()), int(n_open),
                                        ctypes.c_void_p(uniforms.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
                                        _stream_ptr(stream)))
+
+
+def mix_topk(amps, n_qubits, open_q, fixed_q, fixed_bits, k, random_words, out, ws, stream=None):
+    """k most probable bitstrings of a device tensor of 2^len(open_q)
+    complex128 amplitudes mixed with random ones (random_words: uint64 device
+    tensor; out: int64/uint64 device tensor of k + len(random_words) whole
+    bitstrings; ws: tn_mix_workspace_bytes bytes).  Returns P_top, F_top and
+    F_mix_expected."""
+    n_open, n_fixed = len(open_q), len(fixed_q)
+    if int(out.numel()) != k + int(random_words.numel()):
+        raise ValueError("out must hold k + len(random_words) bitstrings")
+    oq = (ctypes.c_int32 * max(1, n_open))(*[int(q) for q in open_q])
+    fq = (ctypes.c_int32 * max(1, n_fixed))(*[int(q) for q in fixed_q])
+    fb = (ctypes.c_uint8 * max(1, n_fixed))(*[int(b) for b in fixed_bits])
+    r = MixResult()
+    _check(library().tn_mix_topk(ctypes.c_void_p(amps.data_ptr()), int(n_qubits), oq, n_open, fq, fb, n_fixed,
+                                 int(k), ctypes.c_void_p(random_words.data_ptr()), int(random_words.numel()),
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel() * ws.element_size(), ctypes.byref(r), _stream_ptr(stream)))
+    return {"P_top": r.P_top, "F_top": r.F_top, "F_mix_expected": r.F_mix_expected}
+
+
+def mix_workspace_bytes(n_open):
+    return int(library().tn_mix_workspace_bytes(int(n_open)))
 
 
 def xeb(amps, n_open, n_qubits, weight=1.0, ks=(), stream=None):

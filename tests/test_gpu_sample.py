@@ -102,3 +102,66 @@ def test_sample_bench_shape_uniform_grid():
     ref, _ = stats.conditional_samples(p, u)
     diff = np.abs(np.bincount(got, minlength=p.size) - np.bincount(ref, minlength=p.size))
     assert diff.max() <= 1 and diff.sum() <= 2 * np.count_nonzero(got != ref)
+
+
+# --- mixing the most probable bitstrings with random ones -----------------
+
+def _mix(amps_np, n_qubits, open_q, fixed_q, bits, k, words_np):
+    import torch
+    from paper_2103_03074_amd import tn
+    n_open = len(open_q)
+    a = torch.from_numpy(np.ascontiguousarray(amps_np, dtype=np.complex128).view(np.float64)).cuda()
+    wd = torch.from_numpy(np.asarray(words_np, dtype=np.uint64).view(np.int64)).cuda()
+    out = torch.empty(k + len(words_np), dtype=torch.int64, device="cuda")
+    ws = torch.empty(tn.mix_workspace_bytes(n_open), dtype=torch.uint8, device="cuda")
+    r = tn.mix_topk(a, n_qubits, open_q, fixed_q, bits, k, wd, out, ws)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint64), r
+
+
+def _check_mix(amps, n_qubits, open_q, fixed_q, bits, k, words):
+    got, r = _mix(amps, n_qubits, open_q, fixed_q, bits, k, words)
+    p = stats.probabilities(amps)
+    top, s, f_top, f_mix = stats.mix_top_with_random(p, k, n_qubits, words)
+    ref_top = stats.full_bitstrings(top, n_qubits, open_q, fixed_q, bits)
+    mask = (1 << n_qubits) - 1 if n_qubits < 64 else (1 << 64) - 1
+    assert [int(x) for x in got[:k]] == ref_top                       # bit-exact selection
+    assert [int(x) for x in got[k:]] == [int(w) & mask for w in words]
+    assert r["P_top"] == pytest.approx(s, rel=1e-12, abs=1e-300)
+    assert r["F_top"] == pytest.approx(f_top, rel=1e-10, abs=1e-10)
+    assert r["F_mix_expected"] == pytest.approx(f_mix, rel=1e-10, abs=1e-10)
+    return r
+
+
+def test_mix_topk_c2_amplitudes(c2_state):
+    """25-qubit state, 10 open qubits: the 20 most probable bitstrings mixed
+    with 1000 random ones, against the oracle's selection and estimate."""
+    w, psi = c2_state
+    amps = sv.amplitudes_from_state(psi, 25, w["open_q"], w["fixed_q"], w["bits"])
+    words = np.random.default_rng(7).integers(0, 2 ** 63, size=1000, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    _say("mix top-k c2, k 20, random 1000")
+    r = _check_mix(amps, 25, w["open_q"], w["fixed_q"], w["bits"], 20, words)
+    _say("mix top-k c2", r)
+    assert r["F_top"] > 1.0                      # the top of a Porter-Thomas sample lies far above the mean
+
+
+@pytest.mark.parametrize("n_open,k", [(20, 220), (20, 0), (12, 4096), (12, 1000)])
+def test_mix_topk_many_blocks_and_ties(n_open, k):
+    """Multi-block selection (2^20 amplitudes), k = 0 and k = all, and many
+    ties (a quarter of the amplitudes zero, one value repeated across
+    blocks) with the threshold inside the tie: the lower indices win."""
+    rng = np.random.default_rng(n_open * 7 + k)
+    L = 1 << n_open
+    a = (rng.normal(size=L) + 1j * rng.normal(size=L)) * 2.0 ** (-n_open / 2)
+    a[rng.choice(L, size=L // 4, replace=False)] = 0.0
+    if 0 < k < L:   # 300 copies of the k-th largest amplitude: the threshold falls inside the tie
+        kth = int(np.argsort(-np.abs(a), kind="stable")[k - 1])
+        a[rng.choice(L, size=300, replace=False)] = a[kth]
+    n_fixed = 5
+    n = n_open + n_fixed
+    open_q = sorted(rng.choice(n, size=n_open, replace=False).tolist())
+    fixed_q = [q for q in range(n) if q not in open_q]
+    bits = rng.integers(0, 2, size=n_fixed).tolist()
+    words = rng.integers(0, 2 ** 63, size=257, dtype=np.uint64)
+    _say("mix top-k, n_open", n_open, "k", k)
+    _check_mix(a, n, open_q, fixed_q, bits, k, words)

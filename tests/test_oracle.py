@@ -336,3 +336,42 @@ def test_adam_first_step_is_signed_lr():
     g = {"w": np.array([0.5, -4.0, 1e-3])}
     mlp.adam_step(p, g, {}, lr=0.1, eps=0.0)
     np.testing.assert_allclose(p["w"], [0.9, -1.9, 2.9], rtol=1e-14)
+
+
+def test_mixing_top_with_random_hand_worked():
+    """Top-k selection and the expected XEB of the mixture on a hand-worked
+    case: p over 2 open qubits of n = 3 (one closed qubit fixed to 1);
+    p = (0.1, 0.4, 0.1, 0.05), k = 2 picks indices 1 (0.4) and then 0 (the
+    tie at 0.1 goes to the lower index); sum 0.5, F_top = 8/2 * 0.5 - 1 = 1,
+    with R = 6 random strings F_mix = (8 * 0.5 + 6) / 8 - 1 = 0.25 = k/N F_top."""
+    p = np.array([0.1, 0.4, 0.1, 0.05])
+    top, s, f_top, f_mix = stats.mix_top_with_random(p, 2, 3, [0] * 6)
+    assert top.tolist() == [0, 1]
+    assert s == pytest.approx(0.5, rel=1e-15)
+    assert f_top == pytest.approx(1.0, rel=1e-15)
+    assert f_mix == pytest.approx(0.25, rel=1e-15)
+    # open qubits 0 and 2, qubit 1 fixed to 1: s2 = 1 -> q0 = 0, q2 = 1 -> 0b011
+    assert stats.full_bitstrings([1, 2], 3, [0, 2], [1], [1]) == [0b011, 0b110]
+
+
+def test_mixing_top_with_random_brute_force_and_uniform():
+    """Against a brute-force scan (repeatedly take the largest remaining
+    probability, lowest index first), and uniform probabilities give
+    F_top = F_mix = 0 whatever k and R."""
+    rng = np.random.default_rng(5)
+    p = rng.exponential(size=64) * 2.0 ** -10
+    p[[3, 9, 17]] = p[40]                              # ties
+    k = 11
+    rest = list(range(64))
+    picked = []
+    for _ in range(k):
+        best = max(rest, key=lambda i: (p[i], -i))
+        picked.append(best)
+        rest.remove(best)
+    top, s, f_top, f_mix = stats.mix_top_with_random(p, k, 16, [0] * 100)
+    assert top.tolist() == sorted(picked)
+    assert s == pytest.approx(sum(p[picked]), rel=1e-14)
+    assert f_mix == pytest.approx(k / (k + 100) * f_top, rel=1e-12)
+    u = np.full(256, 2.0 ** -12)
+    _, _, ft, fm = stats.mix_top_with_random(u, 17, 12, [0] * 50)
+    assert abs(ft) < 1e-12 and abs(fm) < 1e-12
