@@ -1,18 +1,21 @@
 """Learned step-time model: timing corpus, training and evaluation.
 
 The corpus is built from seeded random grid circuits of 36-53 qubits and
-12-20 cycles with 16 open qubits.  Each circuit is planned (FLOP-count model),
-a few launch groups are contracted with the library's per-step HIP-event
-timing on, and every slice-dependent step contributes one sample:
-(features of its shape, log of its mean milliseconds per launch).  Training
+12-20 cycles with 16 open qubits.  Each circuit is planned four ways
+(one-shot and dynamic slicing, with and without branch merging), a few launch
+groups of each plan are contracted with the library's per-step HIP-event
+timing on, and every slice-dependent step contributes one sample: (features
+of its shape, log of its mean milliseconds per launch).  Training
 runs the library's own MLP kernels (forward, backward, Adam).  Evaluation on
 held-out circuits compares
 
 * prediction error (log ms) of the MLP with the FLOP-count model (a
   least-squares fit of log time on log complex multiply-adds per kernel
   class, the paper's cost 2^(nA+nB+nAB) made into a time), and
-* the measured time of the plan each model picks among the same candidate
-  trees and slicings.
+* the measured time of the plan each picks: the FLOP-count model takes the
+  candidate with the fewest multiply-adds (branch merging judged by the
+  roofline estimate), the learned model ranks finalized plan variants (the
+  four cheapest candidates, each unmerged and merged) by predicted job time.
 
 Everything numeric (contraction, timing, training, inference) happens in the
 library; this module only moves data between calls.
@@ -41,11 +44,6 @@ def corpus_circuits(count, seed0=0):
     return cost_model_corpus(count=count, seed0=seed0, n_open=16)
 
 
-def plan_for(c, cost_model=0, model=None, restarts=6, max_log2_size=24, seed=0):
-    return tn.Plan(c["circuit"], c["open_q"], c["fixed_q"], c["bits"], restarts=restarts,
-                   max_log2_size=max_log2_size, cost_model=cost_model, model=model, seed=seed)
-
-
 def time_groups(plan, groups, profile):
     """Contract `groups` launch groups; returns (seconds per group, profile)."""
     import torch
@@ -68,25 +66,75 @@ def time_groups(plan, groups, profile):
     return dt, prof
 
 
-def collect(circs, groups=2, restarts=6, max_log2_size=24):
+# Plan variants timed per training circuit, so that the samples cover the
+# steps of every kind of plan the learned model later ranks: one-shot and
+# dynamic slicing, with and without branch merging.
+VARIANTS = [dict(branch_merge=0, slicing=1), dict(branch_merge=1, slicing=0),
+            dict(branch_merge=0, slicing=2), dict(branch_merge=1, slicing=1)]
+
+
+def collect(circs, groups=2, restarts=6, max_log2_size=24, variants=None):
     X, Y, F, K, owner = [], [], [], [], []
+    variants = VARIANTS if variants is None else variants
     for i, c in enumerate(circs):
         t0 = time.perf_counter()
-        p = plan_for(c, restarts=restarts, max_log2_size=max_log2_size)
-        feats = tn.plan_step_features(p)
-        _, prof = time_groups(p, groups, True)
-        for f, st in zip(feats, prof[:len(feats)]):
-            if st["launches"] == 0 or st["total_ms"] <= 0:
-                continue
-            X.append(f)
-            Y.append(math.log(st["total_ms"] / st["launches"]))
-            F.append(math.log(max(st["cmacs"], 1.0)))
-            K.append(st["kernel"])
-            owner.append(i)
-        log(f"circuit {i}: n={c['n']} m={c['cycles']} steps={len(feats)} ({time.perf_counter() - t0:.1f}s)")
-        p.close()
+        n_steps = 0
+        for v in variants:
+            p = tn.Plan(c["circuit"], c["open_q"], c["fixed_q"], c["bits"], restarts=restarts,
+                        max_log2_size=max_log2_size, seed=0, **v)
+            feats = tn.plan_step_features(p)
+            _, prof = time_groups(p, groups, True)
+            for f, st in zip(feats, prof[:len(feats)]):
+                if st["launches"] == 0 or st["total_ms"] <= 0:
+                    continue
+                X.append(f)
+                Y.append(math.log(st["total_ms"] / st["launches"]))
+                F.append(math.log(max(st["cmacs"], 1.0)))
+                K.append(st["kernel"])
+                owner.append(i)
+            n_steps += len(feats)
+            p.close()
+        log(f"circuit {i}: n={c['n']} m={c['cycles']} steps={n_steps} over {len(variants)} plans "
+            f"({time.perf_counter() - t0:.1f}s)")
     return (np.array(X, dtype=np.float32), np.array(Y, dtype=np.float32), np.array(F), np.array(K),
             np.array(owner))
+
+
+def job_seconds(plan, groups):
+    """Steady-state seconds per launch group (graph replays) times the number
+    of launch groups of the job."""
+    s = plan.stats()
+    g, _ = time_groups(plan, groups, False)
+    return g * 2 ** (s["n_sliced"] - s["batch_log2"])
+
+
+def same_plan(a, b):
+    return (a["cmacs_per_batch"] == b["cmacs_per_batch"] and a["n_sliced"] == b["n_sliced"]
+            and a["batch_log2"] == b["batch_log2"] and a["bytes_per_batch"] == b["bytes_per_batch"])
+
+
+def compare_choices(circs, model, restarts, max_log2_size, groups=2):
+    """Plan each circuit with the FLOP-count model (branch merging judged by
+    the roofline estimate) and with the learned model (ranking finalized plan
+    variants by predicted job time); time both jobs."""
+    rows = []
+    for i, c in enumerate(circs):
+        p0 = tn.Plan(c["circuit"], c["open_q"], c["fixed_q"], c["bits"], restarts=restarts,
+                     max_log2_size=max_log2_size, seed=0, branch_merge=1, cost_model=0)
+        p1 = tn.Plan(c["circuit"], c["open_q"], c["fixed_q"], c["bits"], restarts=restarts,
+                     max_log2_size=max_log2_size, seed=0, branch_merge=1, cost_model=1, model=model)
+        s0, s1 = p0.stats(), p1.stats()
+        j0 = job_seconds(p0, groups)
+        j1 = job_seconds(p1, groups)
+        rows.append({"n": c["n"], "cycles": c["cycles"], "flop_job_s": j0, "mlp_job_s": j1,
+                     "mlp_used": s1["cost_model_used"], "variants_ranked": s1["n_candidates"],
+                     "same_plan": same_plan(s0, s1),
+                     "flop_cmacs_per_slice": s0["cmacs_per_slice"], "mlp_cmacs_per_slice": s1["cmacs_per_slice"]})
+        log(f"held-out {i}: FLOP-chosen job {j0:.4g}s, MLP-chosen job {j1:.4g}s, model used {s1['cost_model_used']}, "
+            f"same plan {rows[-1]['same_plan']}")
+        p0.close()
+        p1.close()
+    return rows
 
 
 def fit_flop_model(F, K, Y):
@@ -152,27 +200,15 @@ def run(n_circuits=200, n_train=None, groups=2, epochs=300, restarts=6, max_log2
         "train_rmse_log_ms_flop": rmse(flop_predict(coef, F, K), Y),
     }
     log("prediction:", res)
-    # plan choice on held-out circuits: same candidates, two rankings
-    rows = []
-    for i, c in enumerate(te):
-        p0 = plan_for(c, 0, None, restarts, max_log2_size)
-        p1 = plan_for(c, 1, model, restarts, max_log2_size)
-        s0, s1 = p0.stats(), p1.stats()
-        g0, _ = time_groups(p0, eval_groups, False)
-        g1, _ = time_groups(p1, eval_groups, False)
-        j0 = g0 * 2 ** (s0["n_sliced"] - s0["batch_log2"])
-        j1 = g1 * 2 ** (s1["n_sliced"] - s1["batch_log2"])
-        rows.append({"n": c["n"], "cycles": c["cycles"], "flop_job_s": j0, "mlp_job_s": j1,
-                     "mlp_used": s1["cost_model_used"], "same_plan": s0["cmacs_per_batch"] == s1["cmacs_per_batch"]
-                     and s0["n_sliced"] == s1["n_sliced"]})
-        log(f"held-out {i}: FLOP-chosen job {j0:.3g}s, MLP-chosen job {j1:.3g}s, model used {s1['cost_model_used']}")
-        p0.close()
-        p1.close()
+    # plan choice on held-out circuits: FLOP-count planning against the
+    # learned model's ranking of finalized plan variants
+    rows = compare_choices(te, model, restarts, max_log2_size, eval_groups)
     j0 = np.array([r["flop_job_s"] for r in rows])
     j1 = np.array([r["mlp_job_s"] for r in rows])
     res.update({"heldout_circuits": len(rows), "heldout_plans": rows,
                 "geomean_speedup_mlp_vs_flop": float(np.exp(np.mean(np.log(j0 / j1)))),
                 "total_job_s_flop": float(j0.sum()), "total_job_s_mlp": float(j1.sum()),
+                "choices_differing": int(sum(not r["same_plan"] for r in rows)),
                 "mlp_fallbacks": int(sum(r["mlp_used"] == 2 for r in rows))})
     return res, model
 

@@ -441,38 +441,6 @@ static void choose_batch(const Network& net, const Tree& tree, const TreeLegs& t
     }
 }
 
-// Shapes (m, n, k, b, kernel, slice-dependent) of every step of a candidate
-// with the given sliced and batch edges, as finalize() would lay them out.
-static std::vector<std::array<int, 6>> candidate_steps(const TreeLegs& tl, const Tree& t, const std::vector<char>& in_s,
-                                                       const std::vector<char>& in_b, tn_precision prec) {
-    const int N = t.n_nodes();
-    std::vector<Legs> lb(N);
-    std::vector<char> dep(N, 0);
-    for (int i = 0; i < t.n_leaves; ++i)
-        for (int e : tl.node[i]) {
-            dep[i] |= in_s[e];
-            if (!in_s[e] || in_b[e]) lb[i].push_back(e);
-        }
-    std::vector<std::array<int, 6>> out;
-    for (size_t s = 0; s < t.lhs.size(); ++s) {
-        int a = t.lhs[s], b = t.rhs[s], c = t.n_leaves + (int)s;
-        dep[c] = dep[a] | dep[b];
-        Legs both = set_inter(lb[a], lb[b]);
-        Legs keep;
-        for (int e : both)
-            if (in_b[e]) keep.push_back(e);
-        lb[c] = set_union(set_xor(lb[a], lb[b]), keep);
-        const int nb = (int)keep.size(), nk = (int)both.size() - nb;
-        int nm = (int)lb[a].size() - (int)both.size(), nn = (int)lb[b].size() - (int)both.size();
-        if (lb[b].size() > lb[a].size()) std::swap(nm, nn);
-        int kernel, tile, split;
-        choose_kernel(nm, nn, nk, nb, prec, kernel, tile, split);
-        if (!dep[c] && kernel == K_SPLITK) kernel = K_SMALL;
-        out.push_back({nm, nn, nk, nb, kernel, (int)dep[c]});
-    }
-    return out;
-}
-
 static std::string finalize(Plan& p) {
     const Network& net = p.net;
     const Tree& t = p.tree;
@@ -869,33 +837,71 @@ static std::string plan_network(Plan& out, const tn_tree* tree, const std::vecto
     out.stats.n_candidates = (int)ranked.size();
     int model_used = 0;
     double predicted = 0;
-    if (opts.cost_model == 1 && cm && ranked.size() > 1) {
-        // learned model: predicted time of the whole job per candidate
+    bool mlp_chose = false;
+    if (opts.cost_model == 1 && cm && cm->predict) {
+        // Learned model: predicted time of the whole job for plan variants
+        // that differ in ways the multiply-add count does not see: the four
+        // cheapest candidates by FLOP count, each as sliced and, with branch
+        // merging on, re-tuned for estimated time (merged).  Every variant is
+        // finalized (batch legs, layouts, kernel per step) and each executed
+        // step is one row of features; variants with a row outside the
+        // model's training support are left out.
+        std::vector<size_t> idx(ranked.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return ranked[a].flops < ranked[b].flops; });
+        struct Var {
+            Tree t;
+            std::vector<int> s;
+            double unmerged;
+            Plan p;
+        };
+        std::vector<Var> vars;
+        const double rate = dense_step_rate(opts.prec);
+        for (size_t i = 0; i < std::min<size_t>(4, idx.size()); ++i) {
+            const Ranked& r = ranked[idx[i]];
+            vars.push_back({r.t, r.s, r.unmerged, Plan()});
+            if (opts.branch_merge && !tree) {
+                std::vector<char> in_s(E, 0);
+                for (int e : r.s) in_s[e] = 1;
+                Tree m = reconfigure(leaf_legs, r.t, in_s, opts.max_log2_size, 8, 16, 1, out.esize, rate);
+                TreeLegs tlm = tree_legs(net, m);
+                if (slice_cost_tl(tlm, m, in_s).max_log2 <= opts.max_log2_size &&
+                    (m.lhs != r.t.lhs || m.rhs != r.t.rhs))
+                    vars.push_back({m, r.s, r.unmerged, Plan()});
+            }
+        }
         std::vector<float> feats;
-        std::vector<std::pair<size_t, size_t>> span;   // rows of each candidate
-        std::vector<std::vector<std::array<int, 6>>> shapes;
-        std::vector<int> groups_log;
-        bool inside = true;
-        for (auto& r : ranked) {
-            TreeLegs tl = tree_legs(net, r.t);
-            std::vector<int> sl = r.s, bt;
-            choose_batch(net, r.t, tl, opts, out.esize, fixed_slicing, sl, bt);
-            std::vector<char> in_s(E, 0), in_b(E, 0);
-            for (int e : sl) in_s[e] = 1;
-            for (int e : bt) in_b[e] = 1;
-            auto st = candidate_steps(tl, r.t, in_s, in_b, opts.prec);
+        std::vector<std::pair<size_t, size_t>> span;
+        std::vector<char> usable(vars.size(), 0);
+        for (size_t v = 0; v < vars.size(); ++v) {
+            Plan& pv = vars[v].p;
+            pv = out;
+            pv.tree = vars[v].t;
+            pv.sliced = vars[v].s;
+            TreeLegs tlv = tree_legs(net, pv.tree);
+            choose_batch(net, pv.tree, tlv, opts, out.esize, fixed_slicing, pv.sliced, pv.batch);
+            pv.batch_log2 = (int)pv.batch.size();
             const size_t r0 = feats.size() / kStepFeatures;
-            for (auto& x : st) {
+            span.push_back({r0, 0});
+            if (!finalize(pv).empty()) continue;
+            bool inside = true;
+            for (const Step& st : pv.steps) {
                 float f[kStepFeatures];
-                step_features(x[0], x[1], x[2], x[3], x[4], out.esize, f);
+                step_features(st.m_log, st.n_log, st.k_log, st.b_log, st.kernel, out.esize, f);
                 if (cm->in_support && !cm->in_support(f)) inside = false;
                 feats.insert(feats.end(), f, f + kStepFeatures);
             }
-            span.push_back({r0, st.size()});
-            shapes.push_back(std::move(st));
-            groups_log.push_back((int)sl.size() - (int)bt.size());
+            span.back().second = pv.steps.size();
+            if (!inside) {
+                feats.resize(r0 * kStepFeatures);
+                span.back().second = 0;
+                continue;
+            }
+            usable[v] = 1;
         }
-        if (!inside) {
+        size_t n_usable = 0;
+        for (char u : usable) n_usable += u;
+        if (n_usable == 0) {
             model_used = 2;
         } else {
             std::vector<float> pred;
@@ -903,23 +909,29 @@ static std::string plan_network(Plan& out, const tn_tree* tree, const std::vecto
             if (!e.empty()) return "cost model: " + e;
             double best = -1;
             size_t bi = 0;
-            for (size_t c = 0; c < ranked.size(); ++c) {
+            for (size_t v = 0; v < vars.size(); ++v) {
+                if (!usable[v]) continue;
+                const Plan& pv = vars[v].p;
                 double dep_ms = 0, inv_ms = 0;
-                for (size_t i = 0; i < span[c].second; ++i) {
-                    const double ms = std::exp((double)pred[span[c].first + i]);
-                    (shapes[c][i][5] ? dep_ms : inv_ms) += ms;
+                for (size_t i = 0; i < span[v].second; ++i) {
+                    const double ms = std::exp((double)pred[span[v].first + i]);
+                    (pv.steps[i].invariant ? inv_ms : dep_ms) += ms;
                 }
-                const double tot = std::exp2((double)groups_log[c]) * dep_ms + inv_ms;
+                const double tot = std::exp2((double)pv.sliced.size() - pv.batch_log2) * dep_ms + inv_ms;
+                if (std::getenv("TN_DEBUG_CANDS"))
+                    std::fprintf(stderr, "mlp variant %zu: predicted %.3f ms per job\n", v, tot);
                 if (best < 0 || tot < best) {
                     best = tot;
-                    bi = c;
+                    bi = v;
                 }
             }
-            out.tree = ranked[bi].t;
-            out.sliced = ranked[bi].s;
-            out.unmerged_cmacs_per_slice = ranked[bi].unmerged;
+            out.tree = vars[bi].t;
+            out.sliced = vars[bi].s;
+            out.unmerged_cmacs_per_slice = vars[bi].unmerged;
             predicted = best;
             model_used = 1;
+            mlp_chose = true;
+            out.stats.n_candidates = (int)n_usable;
         }
     }
     {
@@ -930,7 +942,7 @@ static std::string plan_network(Plan& out, const tn_tree* tree, const std::vecto
     if (out.sliced.size() > 62) return "more than 62 sliced edges needed";
     // branch merging: re-tune the chosen tree for estimated time per slice
     // (more multiply-adds, fewer skinny steps); kept only if faster
-    if (opts.branch_merge && !tree) {
+    if (opts.branch_merge && !tree && !mlp_chose) {
         std::vector<char> in_s(E, 0);
         for (int e : out.sliced) in_s[e] = 1;
         const double rate = dense_step_rate(opts.prec);
