@@ -187,8 +187,9 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
                         (conv ? ",true," : ",false,") + (!conv && nt ? "true>" : "false>");
             e = launch_panel_lp(mode, lt, g, conv, s);
         } else {
-            if (name) *name = "k_panel<" + kcnb + (nt ? "true>" : "false>");
-            e = launch_panel(st.tile & 19, g, s);
+            const bool three = st.tile & 32;
+            if (name) *name = std::string(three ? "k_panel3<" : "k_panel<") + kcnb + (nt ? "true>" : "false>");
+            e = launch_panel(st.tile & 51, g, s);
         }
         if (e != hipSuccess) return std::string("panel launch: ") + hipGetErrorString(e);
         return "";
@@ -561,10 +562,14 @@ std::vector<Candidate> candidates(const Step& st, tn_precision prec) {
         if (panel_ok(st.m_log, st.n_log, st.k_log, st.b_log, prec, t)) {
             c.push_back({K_PANEL, t, 0});
             if (prec == TN_C64) {
-                c.push_back({K_PANEL, t | 16, 0});   // non-temporal A loads
+                c.push_back({K_PANEL, t | 16, 0});        // non-temporal A loads
+                c.push_back({K_PANEL, t | 32, 0});        // three real products per complex product
+                c.push_back({K_PANEL, t | 32 | 16, 0});
             } else {
                 c.push_back({K_PANEL, t | 4, 0});        // FP32 panel in a mixed form
                 c.push_back({K_PANEL, t | 4 | 16, 0});
+                c.push_back({K_PANEL, t | 4 | 32, 0});
+                c.push_back({K_PANEL, t | 4 | 32 | 16, 0});
                 c.push_back({K_PANEL, t | 8, 0});        // A split in registers, no separate pass
                 c.push_back({K_PANEL, t | 8 | 16, 0});
             }

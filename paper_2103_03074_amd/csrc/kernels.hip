@@ -600,8 +600,12 @@ __global__ void __launch_bounds__(256) k_panel(GemmArgs g) {
     constexpr int KP = KC / 2;
     constexpr int CS = 17;
     constexpr int PBN = KC * N / 256;       // B chunk elements per thread
-    __shared__ __attribute__((aligned(16))) float2 Bs[KC * N];
-    __shared__ __attribute__((aligned(16))) float2 Cs[128 * CS];
+    // the B chunks and the output slabs share one LDS buffer (the epilogue
+    // starts with a barrier after the last chunk), for more blocks per CU
+    constexpr int SMEM = KC * N > 128 * CS ? KC * N : 128 * CS;
+    __shared__ __attribute__((aligned(16))) float2 smem[SMEM];
+    float2* const Bs = smem;
+    float2* const Cs = smem;
     const TileIndex ti = tile_index(g);
     const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
     const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
@@ -694,6 +698,129 @@ __global__ void __launch_bounds__(256) k_panel(GemmArgs g) {
             int src_hi = 0;
             for (int i = 8; i < g.ep_n; ++i)
                 if ((j >> (i - 8)) & 1) {
+                    off_hi |= 1ull << g.ep_pos[i];
+                    const int sb = g.ep_src[i];
+                    src_hi += sb < 32 ? CS << sb : 1 << (sb - 32);
+                }
+            C[cb + (off_lo | off_hi)] = Cs[src_lo + src_hi];
+        }
+    }
+    if (g.cmax) tile_max_atomic(mx, g.cmax);
+}
+
+// Complex GEMM on FP32 MFMA with three real products per complex
+// multiply-add instead of four (Gauss's form: T1 = (Re A + Im A) Re B,
+// T2 = Re A (Im B - Re B), T3 = Im A (Re B + Im B); Re C = T1 - T3,
+// Im C = T1 + T2), otherwise as k_panel: 128 rows and 16 NB complex columns
+// per block, A streamed from HBM into MFMA operands, B chunks in LDS.  Each
+// 32x32x2 MFMA covers 32 complex columns (lane r supplies column r), so a
+// K pair costs 3 MFMAs per 32 columns instead of 4.  The rounding error of
+// each output is bounded by the same products' magnitudes as the four-term
+// form, up to a factor of about two.
+template <int KC, int NB, bool NT>
+__global__ void __launch_bounds__(256) k_panel3(GemmArgs g) {
+    constexpr int N = 16 * NB;
+    constexpr int NT3 = N / 32;             // 32-column MFMA tiles
+    constexpr int KP = KC / 2;
+    constexpr int CS = 17;
+    constexpr int PBN = KC * N / 256;
+    constexpr int SMEM = KC * N > 128 * CS ? KC * N : 128 * CS;
+    __shared__ __attribute__((aligned(16))) float2 smem[SMEM];
+    float2* const Bs = smem;
+    float2* const Cs = smem;
+    const TileIndex ti = tile_index(g);
+    const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
+    const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
+                      (ti.beta << g.m_log) + ti.m0;
+    const float2* B = reinterpret_cast<const float2*>(g.B) + slice_offset(g.d_slice, g.sb_n, g.sb_bit, g.sb_pos) +
+                      (ti.beta << g.n_log) + ti.n0;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int r = lane & 31, h = lane >> 5;
+    const uint64_t K = 1ull << g.k_log;
+    float2 a[KP], an[KP], bb[PBN];
+    auto load_a = [&](float2* dst, uint64_t k0) {
+        const float2* src = A + w * 32 + r + (k0 + h) * sAk;
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+            if constexpr (NT) {
+                const floatv2 t = __builtin_nontemporal_load(reinterpret_cast<const floatv2*>(src + (uint64_t)(2 * p) * sAk));
+                dst[p] = make_float2(t.x, t.y);
+            } else {
+                dst[p] = src[(uint64_t)(2 * p) * sAk];
+            }
+        }
+    };
+    auto load_b = [&](uint64_t k0) {
+#pragma unroll
+        for (int i = 0; i < PBN; ++i) {
+            const int e = tid + 256 * i;
+            bb[i] = B[(k0 + e / N) * sBk + (e % N)];
+        }
+    };
+    floatx16 t1[NT3], t2[NT3], t3[NT3];
+#pragma unroll
+    for (int j = 0; j < NT3; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) t1[j][v] = t2[j][v] = t3[j][v] = 0.f;
+    load_b(0);   // B first: see k_panel
+    load_a(a, 0);
+    for (uint64_t k0 = 0; k0 < K; k0 += KC) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PBN; ++i) Bs[tid + 256 * i] = bb[i];
+        __syncthreads();
+        if (k0 + KC < K) {
+            load_b(k0 + KC);
+            load_a(an, k0 + KC);
+        }
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+            const float a1 = a[p].x + a[p].y;
+#pragma unroll
+            for (int j = 0; j < NT3; ++j) {
+                const float2 b = Bs[(2 * p + h) * N + j * 32 + r];
+                t1[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b.x, t1[j], 0, 0, 0);
+                t2[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].x, b.y - b.x, t2[j], 0, 0, 0);
+                t3[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].y, b.x + b.y, t3[j], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < KP; ++p) a[p] = an[p];
+    }
+    // epilogue: 16-column slabs (tile bits m0..m6, n0..n3); the lanes holding
+    // a slab's columns stage it
+    uint64_t off_lo = 0;
+    int src_lo = 0;
+    for (int i = 0; i < 8; ++i)
+        if ((tid >> i) & 1) {
+            off_lo |= 1ull << g.ep_pos[i];
+            const int sb = g.ep_src[i];
+            src_lo += sb < 32 ? CS << sb : 1 << (sb - 32);
+        }
+    float mx = 0.f;
+    const uint64_t cbase = deposit(ti.m0, g.cpm, 7, g.m_log) + deposit(ti.beta, g.cpb, 0, g.b_log);
+    float2* C = reinterpret_cast<float2*>(g.C);
+#pragma unroll
+    for (int sl = 0; sl < 2 * NT3; ++sl) {
+        const int j = sl >> 1, hf = sl & 1;
+        __syncthreads();
+        if ((r >> 4) == hf) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = w * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+                const float2 c = make_float2(t1[j][v] - t3[j][v], t1[j][v] + t2[j][v]);
+                Cs[row * CS + (r & 15)] = c;
+                mx = fmaxf(mx, fmaxf(fabsf(c.x), fabsf(c.y)));
+            }
+        }
+        __syncthreads();
+        const uint64_t cb = cbase + deposit(ti.n0 + ((uint64_t)sl << 4), g.cpn, 4, g.n_log);
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            uint64_t off_hi = 0;
+            int src_hi = 0;
+            for (int i = 8; i < g.ep_n; ++i)
+                if ((jj >> (i - 8)) & 1) {
                     off_hi |= 1ull << g.ep_pos[i];
                     const int sb = g.ep_src[i];
                     src_hi += sb < 32 ? CS << sb : 1 << (sb - 32);
@@ -928,8 +1055,12 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
     constexpr int CS = 17;
     constexpr int PBN = KC * N / 256;
     constexpr int NS = KC / 8;               // MFMA steps (8 complex k) per chunk
-    __shared__ __attribute__((aligned(16))) uint32_t Bw[PL][NR * RS];
-    __shared__ __attribute__((aligned(16))) float2 Cs[128 * CS];
+    // B' planes and the output slabs share one LDS buffer (the epilogue
+    // starts with a barrier after the last chunk), for more blocks per CU
+    constexpr int BW_WORDS = PL * NR * RS, CS_WORDS = 2 * 128 * CS;
+    __shared__ __attribute__((aligned(16))) uint32_t smem[BW_WORDS > CS_WORDS ? BW_WORDS : CS_WORDS];
+    uint32_t* const Bw[2] = {smem, smem + (PL - 1) * NR * RS};
+    float2* const Cs = reinterpret_cast<float2*>(smem);
     const TileIndex ti = tile_index(g);
     const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
     const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
@@ -1323,6 +1454,16 @@ hipError_t launch_skinny(const GemmArgs& g, hipStream_t s) {
 }
 
 template <bool NT>
+static void launch_panel3_t(int tile, const GemmArgs& g, dim3 grid, hipStream_t s) {
+    switch (tile & 3) {
+        case 0: hipLaunchKernelGGL((k_panel3<32, 4, NT>), grid, dim3(256), 0, s, g); break;
+        case 1: hipLaunchKernelGGL((k_panel3<16, 4, NT>), grid, dim3(256), 0, s, g); break;
+        case 2: hipLaunchKernelGGL((k_panel3<32, 2, NT>), grid, dim3(256), 0, s, g); break;
+        default: hipLaunchKernelGGL((k_panel3<16, 2, NT>), grid, dim3(256), 0, s, g); break;
+    }
+}
+
+template <bool NT>
 static void launch_panel_t(int tile, const GemmArgs& g, dim3 grid, hipStream_t s) {
     switch (tile & 3) {
         case 0: hipLaunchKernelGGL((k_panel<32, 4, NT>), grid, dim3(256), 0, s, g); break;
@@ -1334,14 +1475,20 @@ static void launch_panel_t(int tile, const GemmArgs& g, dim3 grid, hipStream_t s
 
 hipError_t launch_panel(int tile, const GemmArgs& g, hipStream_t s) {
     // tile: bit 0 -> KC = 16 (else 32), bit 1 -> NB = 2 (else 4), bit 4 ->
-    // non-temporal A loads
+    // non-temporal A loads, bit 5 -> three real products per complex
+    // multiply-add (k_panel3)
     const int kc_log = (tile & 1) ? 4 : 5, nb_log = (tile & 2) ? 1 : 2;
-    if (tile < 0 || (tile & ~19) || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) || g.k_log < kc_log ||
+    if (tile < 0 || (tile & ~51) || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) || g.k_log < kc_log ||
         g.ep_n != 11 || g.split_log != 0)
         return hipErrorInvalidValue;
     const dim3 grid = grid_for(tile_blocks(g));
-    if (tile & 16) launch_panel_t<true>(tile, g, grid, s);
-    else launch_panel_t<false>(tile, g, grid, s);
+    if (tile & 32) {
+        if (tile & 16) launch_panel3_t<true>(tile, g, grid, s);
+        else launch_panel3_t<false>(tile, g, grid, s);
+    } else {
+        if (tile & 16) launch_panel_t<true>(tile, g, grid, s);
+        else launch_panel_t<false>(tile, g, grid, s);
+    }
     return hipGetLastError();
 }
 

@@ -38,7 +38,9 @@ inline bool skinny_ok(int m, int n, int k, int b, tn_precision prec) {
 // bit 2 -> FP32 MFMA even in a mixed form (the autotuner may pick it where
 // the low-precision GEMM is not faster), bit 3 -> a mixed-form GEMM splits A
 // in registers instead of reading planes split by a separate pass, bit 4 ->
-// A loaded with non-temporal loads (FP32 panels and A split in registers).
+// A loaded with non-temporal loads (FP32 panels and A split in registers),
+// bit 5 -> complex64 panel with three real products per complex
+// multiply-add (Gauss's form) instead of four.
 constexpr int kNumPanelTiles = 4;
 inline int panel_kc_log(int tile) { return (tile & 1) ? 4 : 5; }
 inline int panel_tn_log(int tile) { return (tile & 2) ? 5 : 6; }
