@@ -192,13 +192,30 @@ int bisect(const Graph& g, const std::vector<int>& vs, double eps, std::mt19937_
 
 }  // namespace
 
-Tree partition_tree(const std::vector<Legs>& leaf_legs, uint64_t seed, double eps, int leaf_size, int open_w) {
+Tree partition_tree(const std::vector<Legs>& leaf_legs, uint64_t seed, double eps, int leaf_size, int open_w,
+                    int time_cap, int space_cap) {
     const int L = (int)leaf_legs.size();
     Graph g = leaf_graph(leaf_legs, open_w);
     std::mt19937_64 rng(seed * 0x2545F4914F6CDD1DULL + 99);
     std::vector<int> side(L + 1, 0), mark(L + 1, 0);
     Tree t;
     t.n_leaves = L;
+    // legs of a group of leaves: bonds with one end inside (open legs count;
+    // the virtual output vertex L is not a leaf)
+    auto part_legs = [&](const std::vector<int>& part) {
+        Legs all;
+        for (int v : part)
+            if (v != L) all.insert(all.end(), leaf_legs[v].begin(), leaf_legs[v].end());
+        std::sort(all.begin(), all.end());
+        Legs out;
+        for (size_t i = 0; i < all.size();) {
+            size_t j = i;
+            while (j < all.size() && all[j] == all[i]) ++j;
+            if (j - i == 1) out.push_back(all[i]);
+            i = j;
+        }
+        return out;
+    };
     // recursive bisection, emitting steps bottom-up; the virtual output
     // vertex L takes part in the cuts but is never contracted
     std::function<int(std::vector<int>)> rec = [&](std::vector<int> vs) -> int {
@@ -222,9 +239,33 @@ Tree partition_tree(const std::vector<Legs>& leaf_legs, uint64_t seed, double ep
             }
             return id[st.n_nodes() - 1];
         }
-        bisect(g, vs, eps, rng, side, mark);
         std::vector<int> a, b;
-        for (int v : vs) (side[v] == 0 ? a : b).push_back(v);
+        if (time_cap <= 0 && space_cap <= 0) {
+            bisect(g, vs, eps, rng, side, mark);
+            for (int v : vs) (side[v] == 0 ? a : b).push_back(v);
+        } else {
+            // time and space caps on this bisection's own contraction:
+            // retry with other imbalances until within both caps (or keep
+            // the split with the smallest excess, then the smallest cut)
+            int best_excess = -1, best_cut = 0;
+            for (int tr = 0; tr < 6; ++tr) {
+                const double e = tr == 0 ? eps : std::min(0.9, eps * (1.0 + 0.5 * tr));
+                const int cut = bisect(g, vs, e, rng, side, mark);
+                std::vector<int> ta, tb;
+                for (int v : vs) (side[v] == 0 ? ta : tb).push_back(v);
+                const Legs la = part_legs(ta), lb = part_legs(tb);
+                const int u = (int)set_union(la, lb).size(), o = (int)set_xor(la, lb).size();
+                const int excess = (time_cap > 0 ? std::max(0, u - time_cap) : 0) +
+                                   (space_cap > 0 ? std::max(0, o - space_cap) : 0);
+                if (best_excess < 0 || excess < best_excess || (excess == best_excess && cut < best_cut)) {
+                    best_excess = excess;
+                    best_cut = cut;
+                    a = ta;
+                    b = tb;
+                }
+                if (excess == 0) break;
+            }
+        }
         if (a.empty() || b.empty()) {   // degenerate split: halve by order
             a.assign(vs.begin(), vs.begin() + vs.size() / 2);
             b.assign(vs.begin() + vs.size() / 2, vs.end());

@@ -754,6 +754,17 @@ static std::string plan_network(Plan& out, const tn_tree* tree, const std::vecto
                 cands.push_back(greedy_tree(leaf_legs, opts.seed * 1000003ULL + r, alpha, temp));
             }
         }
+        // hierarchical bipartition under time and space caps on every
+        // bisection (appendix A): the space cap is the memory target plus a
+        // slicing budget of 4, 8 or 12 legs, the time cap 8 above it
+        for (int r = 0; r < (R + 3) / 4; ++r) {
+            const int space_cap = opts.max_log2_size + 4 * (1 + r % 3);
+            const double eps = r == 0 ? 0.3 : ue(rng);
+            const int leaf = r == 0 ? 60 : ul(rng);   // the paper's finest sub-graphs hold up to 60 tensors
+            const int open_w = r == 0 ? 2 : (int)(rng() % 4);
+            cands.push_back(partition_tree(leaf_legs, opts.seed * 1000003ULL + 7919 + r, eps, leaf, open_w,
+                                           space_cap + 8, space_cap));
+        }
         if (extra && extra->n_leaves == L) cands.push_back(*extra);
     }
     if (L == 1) {

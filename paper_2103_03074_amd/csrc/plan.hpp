@@ -68,8 +68,12 @@ Tree greedy_tree(const std::vector<Legs>& leaf_legs, uint64_t seed, double alpha
 
 // Order from recursive min-cut bisection (leaf groups of <= leaf_size tensors
 // contracted greedily); eps is the allowed size imbalance of each bisection.
+// time_cap / space_cap (log2; 0 = none): every bisection's own contraction
+// (the two parts joined) should stay within 2^time_cap multiply-adds and a
+// 2^space_cap output; bisections over a cap are retried with other seeds
+// and imbalances, keeping the one closest to the caps.
 Tree partition_tree(const std::vector<Legs>& leaf_legs, uint64_t seed, double eps, int leaf_size,
-                    int open_w);
+                    int open_w, int time_cap = 0, int space_cap = 0);
 
 // Subtree reconfiguration: repeatedly replace subtrees of up to max_frontier
 // frontier tensors by their optimal order (cost per slice with the edges in

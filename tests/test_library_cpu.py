@@ -166,7 +166,11 @@ def test_branch_merging_decided_per_launch_group():
     plain = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], branch_merge=0, **kw).stats()
     merged = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], branch_merge=1, **kw).stats()
     assert merged["batch_log2"] == 8
-    assert merged["cmacs_per_batch"] <= 2 * plain["cmacs_per_batch"]
+    # merging may trade multiply-adds for bytes, within bounds far from the
+    # 100x blow-up of the per-slice estimate
+    assert merged["cmacs_per_batch"] <= 4 * plain["cmacs_per_batch"]
+    if merged["cmacs_per_batch"] != plain["cmacs_per_batch"]:
+        assert merged["bytes_per_batch"] < plain["bytes_per_batch"]
     # the 40-qubit bench plan does merge: more multiply-adds, fewer bytes
     w3 = rqc.workload("c3_5x8_m16")
     kw3 = dict(restarts=16, n_slice_edges=16, seed=0)
