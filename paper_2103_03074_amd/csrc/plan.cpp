@@ -1340,7 +1340,17 @@ std::string plan_to_json(const Plan& p) {
           << ",\"m\":" << s.m_log << ",\"n\":" << s.n_log << ",\"k\":" << s.k_log << ",\"batch\":" << s.b_log
           << ",\"invariant\":" << (s.invariant ? "true" : "false") << ",\"kernel\":" << s.kernel
           << ",\"tile\":" << s.tile << ",\"splitk\":" << s.splitk_log << ",\"cmacs\":" << s.cmacs
-          << ",\"bytes\":" << s.bytes << "}";
+          << ",\"bytes\":" << s.bytes;
+        // output address bit of each m, n and batch index (C layout)
+        auto arr = [&](const char* key, const std::vector<int>& v) {
+            o << ",\"" << key << "\":[";
+            for (size_t j = 0; j < v.size(); ++j) o << (j ? "," : "") << v[j];
+            o << "]";
+        };
+        arr("c_pos_m", s.c_pos_m);
+        arr("c_pos_n", s.c_pos_n);
+        arr("c_pos_b", s.c_pos_b);
+        o << "}";
     }
     const tn_plan_stats& st = p.stats;
     o << "],\"stats\":{\"n_sliced\":" << st.n_sliced << ",\"batch_log2\":" << st.batch_log2

@@ -743,3 +743,4 @@ def test_c3_many_group_graph_closed_form():
     ref = sum(cf.product_amplitudes(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], sliced, j)
               for j in range(lo, hi))
     _check(got, ref, C128_TOL, "c3 many-group graph", skewed=True)
+
