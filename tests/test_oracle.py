@@ -175,6 +175,43 @@ def test_slice_values_order_invariant():
         np.testing.assert_allclose(a, b, atol=1e-13)
 
 
+def test_pairwise_contraction_against_direct_loops():
+    """The oracle's pairwise step (a library tensordot over the shared
+    labels) against the definition written as loops over every index
+    assignment, on random tensors whose shared labels sit at arbitrary axes."""
+    import itertools
+    rng = np.random.default_rng(3)
+    la, lb = ["a", "s1", "b", "s2"], ["s2", "c", "s1"]
+    ta = rng.normal(size=(2,) * 4) + 1j * rng.normal(size=(2,) * 4)
+    tb = rng.normal(size=(2,) * 3) + 1j * rng.normal(size=(2,) * 3)
+    t, labs = nw.contract_pair(ta, la, tb, lb)
+    assert labs == ["a", "b", "c"]
+    for a, b, c in itertools.product((0, 1), repeat=3):
+        ref = 0j
+        for s1, s2 in itertools.product((0, 1), repeat=2):
+            ref += ta[a, s1, b, s2] * tb[s2, c, s1]
+        assert abs(t[a, b, c] - ref) < 1e-14
+
+
+def test_slice_values_invariant_under_the_planners_tree():
+    """Slices of the 25-qubit workload contracted by the oracle in its own
+    greedy order and in the order of the planner's exported tree (a schedule
+    only: every value is the oracle's) agree to 1e-12; the large workloads'
+    per-slice checks use the planner's tree as the oracle's schedule."""
+    from paper_2103_03074_amd import tn
+    w = rqc.workload("c2_5x5_m16")
+    p = tn.Plan(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], n_slice_edges=8, restarts=4, seed=0,
+                branch_merge=1)
+    ex = p.export()
+    sliced = [tuple(e) for e in ex["sliced"]]
+    tree = list(zip(ex["lhs"], ex["rhs"]))
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    sub = nw.slice_network(net, sliced, nw.slice_values(sliced, 77))
+    a = nw.contract(sub)
+    b = nw.contract(sub, tree)
+    assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_product_circuit_closed_form(seed):
     c = rqc.product_circuit(rqc.rect_layout(3, 4), 8, seed=seed)
