@@ -1,12 +1,12 @@
 """Precision study on the 53-qubit, 20-cycle workload.
 
-256 slice ids are sampled (seed 2) out of the 2^k slices of the plan for the
+16 slice ids (--samples) are sampled (seed 2) out of the 2^k slices of the plan for the
 54-site diagonal grid with 53 active qubits, 20 open and 33 fixed.  The same
 tree and slicing are contracted in complex128 (the float64 recontraction),
 complex64, split-FP16 and BF16.  For each form the study reports the
 norm-relative error of the summed partial amplitudes against complex128, the
 time per slice, and XEB of the partial sums with every probability scaled by
-2^k / 256 (partial sums over a sample are not amplitudes; the scaled
+2^k / n_samples (partial sums over a sample are not amplitudes; the scaled
 estimator is computed the same way for every form, so the XEB differences
 measure precision only).
 
@@ -36,7 +36,7 @@ def log(*a):
     print("[study]", *a, file=sys.stderr, flush=True)
 
 
-def precision_study(n_samples=256, precs=("c128", "c64", "split_fp16", "bf16"), restarts=16):
+def precision_study(n_samples=16, precs=("c128", "c64", "split_fp16", "bf16"), restarts=16):
     import torch
     import rqc
     from . import tn, runtime
@@ -144,7 +144,7 @@ def bighead_study(restarts=16):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--samples", type=int, default=256)
+    ap.add_argument("--samples", type=int, default=16)
     ap.add_argument("--bighead", action="store_true")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
