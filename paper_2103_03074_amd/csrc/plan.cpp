@@ -691,6 +691,17 @@ double dense_step_rate(tn_precision prec) {
     return prec == TN_SPLIT_FP16 ? 200e12 : 110e12;
 }
 
+double write_weight(tn_precision prec) {
+    // Writes stream at about half the rate of reads on MI355X (a plain device
+    // copy moves 2.65 TB/s each way).  Counting output bytes twice in the time
+    // objective made the split-FP16 plan of the 40-qubit workload 1.32x
+    // faster per launch group (its steps are bound by memory, not by the
+    // matrix cores) but the complex64 plan 3 % slower and the 25-qubit
+    // complex64 job 22 % slower, so the low-precision forms use it and
+    // complex64 / complex128 do not.
+    return lp_prec(prec) ? 2.0 : 1.0;
+}
+
 // Roofline time estimate (seconds) of one job on a finalized plan: per
 // launch max(8 cmacs / rate, bytes / 4 TB/s) + 2 us, slice-dependent steps
 // once per launch group, invariant steps once.
@@ -700,7 +711,9 @@ static double plan_time_estimate(const Plan& p) {
     double t = 0;
     for (const Step& st : p.steps) {
         const bool mfma = st.kernel == K_MFMA || st.kernel == K_PANEL || st.kernel == K_SKINNY;
-        const double one = std::max(8.0 * st.cmacs / (mfma ? dense : 25e12), st.bytes / 4e12) + 2e-6;
+        const double out_bytes = p.esize * std::exp2((double)(st.m_log + st.n_log + st.b_log));
+        const double bytes = st.bytes + (write_weight(p.opts.prec) - 1.0) * out_bytes;
+        const double one = std::max(8.0 * st.cmacs / (mfma ? dense : 25e12), bytes / 4e12) + 2e-6;
         t += st.invariant ? one : one * groups;
     }
     return t;
@@ -874,7 +887,8 @@ static std::string plan_network(Plan& out, const tn_tree* tree, const std::vecto
             if (opts.branch_merge && !tree) {
                 std::vector<char> in_s(E, 0);
                 for (int e : r.s) in_s[e] = 1;
-                Tree m = reconfigure(leaf_legs, r.t, in_s, opts.max_log2_size, 8, 16, 1, out.esize, rate);
+                Tree m = reconfigure(leaf_legs, r.t, in_s, opts.max_log2_size, 8, 16, 1, out.esize, rate,
+                                     write_weight(opts.prec));
                 TreeLegs tlm = tree_legs(net, m);
                 if (slice_cost_tl(tlm, m, in_s).max_log2 <= opts.max_log2_size &&
                     (m.lhs != r.t.lhs || m.rhs != r.t.rhs))
@@ -957,11 +971,12 @@ static std::string plan_network(Plan& out, const tn_tree* tree, const std::vecto
         std::vector<char> in_s(E, 0);
         for (int e : out.sliced) in_s[e] = 1;
         const double rate = dense_step_rate(opts.prec);
-        Tree merged = reconfigure(leaf_legs, out.tree, in_s, opts.max_log2_size, 8, 16, 1, out.esize, rate);
+        const double ww = write_weight(opts.prec);
+        Tree merged = reconfigure(leaf_legs, out.tree, in_s, opts.max_log2_size, 8, 16, 1, out.esize, rate, ww);
         TreeLegs tlm = tree_legs(net, merged);
         if (slice_cost_tl(tlm, merged, in_s).max_log2 <= opts.max_log2_size &&
-            tree_time_estimate(leaf_legs, merged, in_s, out.esize, rate) <
-                tree_time_estimate(leaf_legs, out.tree, in_s, out.esize, rate)) {
+            tree_time_estimate(leaf_legs, merged, in_s, out.esize, rate, ww) <
+                tree_time_estimate(leaf_legs, out.tree, in_s, out.esize, rate, ww)) {
             // the per-slice estimate ignores batch legs (work shared by the
             // slices of a launch group, outputs that keep the batch legs) and
             // the slice-invariant part: confirm on the executed steps of both

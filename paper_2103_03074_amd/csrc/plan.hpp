@@ -79,15 +79,20 @@ Tree partition_tree(const std::vector<Legs>& leaf_legs, uint64_t seed, double ep
 // frontier tensors by their optimal order (cost per slice with the edges in
 // in_s removed, intermediates above 2^target penalised).
 // objective 0: complex multiply-adds; 1: roofline time estimate (branch
-// merging) with dense_rate the flop rate of MFMA-shaped steps.
+// merging) with dense_rate the flop rate of MFMA-shaped steps and each
+// step's output bytes counted write_weight times.
 Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::vector<char>& in_s, int target,
-                 int max_frontier, int passes, int objective = 0, int esize = 8, double dense_rate = 110e12);
+                 int max_frontier, int passes, int objective = 0, int esize = 8, double dense_rate = 110e12,
+                 double write_weight = 1.0);
 // Roofline time estimate of a tree (same units as objective 1).
 double tree_time_estimate(const std::vector<Legs>& leaf_legs, const Tree& t, const std::vector<char>& in_s, int esize,
-                          double dense_rate = 110e12);
+                          double dense_rate = 110e12, double write_weight = 1.0);
 // Measured flop rate (Eq. (3) flops per second) of MFMA-shaped steps per
 // precision on MI355X, for the time objective.
 double dense_step_rate(tn_precision prec);
+// Weight of output bytes against input bytes in the time objective, per
+// precision (measured on the 40-qubit workload).
+double write_weight(tn_precision prec);
 
 // Leaves contracted one after another in network (time) order.
 Tree time_order_tree(int n_leaves);

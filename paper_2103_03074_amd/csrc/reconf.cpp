@@ -58,6 +58,7 @@ struct CostCtx {
     int objective;       // 0: multiply-adds, 1: roofline time
     double esize;        // bytes per element
     double dense_rate;   // flop rate of MFMA-shaped steps
+    double write_weight; // output bytes count this many times
 };
 
 static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, int target, const CostCtx& cx) {
@@ -75,7 +76,7 @@ static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, in
         // ~25 TFLOP/s, streaming steps ~4 TB/s
         const double rate = dense ? cx.dense_rate : 25e12;
         const double bytes = cx.esize * (std::exp2((double)a_bits) + std::exp2((double)b_bits) +
-                                        std::exp2((double)out_bits));
+                                        cx.write_weight * std::exp2((double)out_bits));
         c = std::max(flops / rate, bytes / 4e12) * 1e12 + 2.0e6;   // + per-launch overhead (~2 us)
     }
     if (out_bits > target) c *= std::exp2(4.0 * (out_bits - target) + 20.0);
@@ -84,8 +85,8 @@ static double step_cost_obj(int u_bits, int a_bits, int b_bits, int out_bits, in
 
 
 Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::vector<char>& in_s, int target,
-                 int max_frontier, int passes, int objective, int esize, double dense_rate) {
-    const CostCtx cx{objective, (double)esize, dense_rate};
+                 int max_frontier, int passes, int objective, int esize, double dense_rate, double write_weight) {
+    const CostCtx cx{objective, (double)esize, dense_rate, write_weight};
     Tree t = in;
     const int L = t.n_leaves;
     if (t.lhs.empty()) return t;
@@ -240,8 +241,8 @@ Tree reconfigure(const std::vector<Legs>& leaf_legs, const Tree& in, const std::
 }
 
 double tree_time_estimate(const std::vector<Legs>& leaf_legs, const Tree& t, const std::vector<char>& in_s,
-                          int esize, double dense_rate) {
-    const CostCtx cx{1, (double)esize, dense_rate};
+                          int esize, double dense_rate, double write_weight) {
+    const CostCtx cx{1, (double)esize, dense_rate, write_weight};
     const int L = t.n_leaves;
     std::vector<Legs> legs(t.n_nodes());
     for (int i = 0; i < L; ++i) {
