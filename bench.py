@@ -196,8 +196,10 @@ def main():
     ap.add_argument("--batch-log2", type=int, default=-1)
     ap.add_argument("--branch-merge", type=int, default=1,
                     help="re-tune the tree for estimated time (merges small branches first)")
-    ap.add_argument("--tune-cache", default=None,
-                    help="autotune cache file (read, and extended with new decisions)")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2103_03074_amd", "tune", "gfx950.txt"),
+                    help="autotune cache file (read, and extended with new decisions); the default is the "
+                         "committed cache written by this bench on MI355X, so runs and profiles use the same "
+                         "kernel per step shape (\"\" to re-tune every shape)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-full-job", action="store_true", help="skip the measured full job")
@@ -250,7 +252,7 @@ def main():
         n_tuned, t_tune = 0, 0.0
         if not args.no_autotune:
             t0 = time.perf_counter()
-            n_tuned = plan.autotune(ws, acc, args.tune_cache, reps=5)
+            n_tuned = plan.autotune(ws, acc, args.tune_cache or None, reps=5)
             t_tune = time.perf_counter() - t0
             log(f"{prec}: autotuned {n_tuned} step shapes in {t_tune:.1f}s")
             s = plan.stats()
@@ -364,6 +366,7 @@ def main():
                    "slices_per_step": main_run["groups_per_step"] << s["batch_log2"],
                    "largest_intermediate_log2": s["max_log2_size"], "restarts": args.restarts,
                    "branch_merge": args.branch_merge,
+                   "tune_cache": os.path.relpath(args.tune_cache, ROOT) if args.tune_cache else None,
                    "launch": "graph replay per launch group" if args.launch == "graph" else "eager",
                    "events_pass_groups": main_run["events_groups"]},
         "pct_mfma_peak": m["pct_of_form_mfma_peak"],

@@ -60,14 +60,14 @@ def short_name(name):
 
 
 def read_csv(directory, suffix):
-    paths = sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True))
+    """Rows of the newest *suffix file under directory (one profiled process
+    per directory; older files left by earlier runs are ignored)."""
+    paths = glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True)
     if not paths:
         raise SystemExit(f"no *{suffix} under {directory}")
-    rows = []
-    for p in paths:
-        with open(p, newline="") as f:
-            rows += list(csv.DictReader(f))
-    return rows
+    newest = max(paths, key=os.path.getmtime)
+    with open(newest, newline="") as f:
+        return list(csv.DictReader(f))
 
 
 def col(row, *names):
