@@ -177,9 +177,16 @@ def predict(model, X):
     return y.cpu().numpy()
 
 
-def run(n_circuits=200, n_train=None, groups=2, epochs=300, restarts=6, max_log2_size=24, eval_groups=2):
+def run(n_circuits=200, n_train=None, groups=2, epochs=300, restarts=6, max_log2_size=24, eval_groups=2,
+        max_qubits=64):
+    """n_circuits circuits of the corpus with at most max_qubits qubits (the
+    corpus is drawn in seed order and filtered), 80 % for training."""
     n_train = n_train if n_train is not None else int(round(0.8 * n_circuits))
-    circs = corpus_circuits(n_circuits)
+    circs = []
+    pool = 0
+    while len(circs) < n_circuits:
+        pool += 4 * n_circuits
+        circs = [c for c in corpus_circuits(pool) if c["n"] <= max_qubits][:n_circuits]
     tr, te = circs[:n_train], circs[n_train:]
     log(f"collecting timings on {len(tr)} training circuits")
     X, Y, F, K, _ = collect(tr, groups, restarts, max_log2_size)
@@ -219,11 +226,13 @@ def main():
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--restarts", type=int, default=6)
     ap.add_argument("--max-log2-size", type=int, default=24)
+    ap.add_argument("--max-qubits", type=int, default=64, help="use only corpus circuits with at most this many qubits")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available()
-    res, _ = run(args.circuits, epochs=args.epochs, restarts=args.restarts, max_log2_size=args.max_log2_size)
+    res, _ = run(args.circuits, epochs=args.epochs, restarts=args.restarts, max_log2_size=args.max_log2_size,
+                 max_qubits=args.max_qubits)
     text = json.dumps(res)
     print(text, flush=True)
     if args.out:
