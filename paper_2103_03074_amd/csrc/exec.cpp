@@ -172,8 +172,9 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
     if (st.kernel == K_PANEL) {
         g.tn = panel_tn_log(st.tile);
         // names as profilers show the device functions (template arguments)
+        const int tnl = panel_tn_log(st.tile);
         const std::string kcnb = std::string(panel_kc_log(st.tile) == 5 ? "32," : "16,") +
-                                 (panel_tn_log(st.tile) == 6 ? "4," : "2,");
+                                 (tnl == 7 ? "8," : (tnl == 6 ? "4," : "2,"));
         const bool nt = st.tile & 16;
         hipError_t e;
         if (!panel_fp32(st.tile, p.opts.prec)) {
@@ -181,7 +182,7 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
             uint32_t* conv = (ws && st.conv_off != ~uint64_t(0) && !(st.tile & 8))
                                  ? reinterpret_cast<uint32_t*>((unsigned char*)ws + st.conv_off * (uint64_t)p.esize)
                                  : nullptr;
-            const int lt = conv ? (st.tile & 3) : (st.tile & 19);
+            const int lt = conv ? (st.tile & 67) : (st.tile & 83);
             if (name)
                 *name = std::string(conv ? "k_lp_convert_a+" : "") + "k_panel_lp<" + kcnb + std::to_string(mode) +
                         (conv ? ",true," : ",false,") + (!conv && nt ? "true>" : "false>");
@@ -574,6 +575,11 @@ std::vector<Candidate> candidates(const Step& st, tn_precision prec) {
                 c.push_back({K_PANEL, t | 8 | 16, 0});
             }
         }
+    if (lp_prec(prec) && panel_ok(st.m_log, st.n_log, st.k_log, st.b_log, prec, 64 | 1)) {
+        c.push_back({K_PANEL, 64 | 1, 0});   // 128 complex columns per block, KC = 16
+        c.push_back({K_PANEL, 64 | 1 | 8, 0});
+        c.push_back({K_PANEL, 64 | 1 | 8 | 16, 0});
+    }
     c.push_back({K_SMALL, 0, 0});
     if (st.k_log <= 4 && st.n_log <= 4 && st.m_log >= (prec == TN_C128 ? 8 : 9) &&
         st.b_log <= 16)

@@ -474,6 +474,33 @@ __global__ void __launch_bounds__(256) k_mfma_c64(GemmArgs g) {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatv2 __attribute__((ext_vector_type(2)));
 
+// The three high tile bits of the slab epilogues (taken from the unrolled
+// store index j): address bit and LDS source offset of each (cs: LDS row
+// stride in complex elements), read once instead of once per stored element.
+struct EpHigh {
+    uint64_t pos[3];
+    int src[3];
+    __device__ __forceinline__ uint64_t off(int j) const {
+        return ((j & 1) ? pos[0] : 0) | ((j & 2) ? pos[1] : 0) | ((j & 4) ? pos[2] : 0);
+    }
+    __device__ __forceinline__ int from(int j) const {
+        return ((j & 1) ? src[0] : 0) + ((j & 2) ? src[1] : 0) + ((j & 4) ? src[2] : 0);
+    }
+};
+
+__device__ __forceinline__ EpHigh ep_high(const GemmArgs& g, int first, int cs) {
+    EpHigh e;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int i = first + b;
+        const bool on = i < g.ep_n;
+        const int sb = g.ep_src[i];
+        e.pos[b] = on ? 1ull << g.ep_pos[i] : 0;
+        e.src[b] = on ? (sb < 32 ? cs << sb : 1 << (sb - 32)) : 0;
+    }
+    return e;
+}
+
 // Big-times-small steps with N = 16..64 and K = 2..64 complex (the steps that
 // dominate once small branches are merged, appendix B): HBM-bound, so A is
 // streamed from global memory straight into MFMA operands and read once.
@@ -518,6 +545,7 @@ __global__ void __launch_bounds__(256) k_skinny(GemmArgs g) {
             const int sb = g.ep_src[i];
             src_lo += sb < 32 ? CS << sb : 1 << (sb - 32);
         }
+    const EpHigh eh = ep_high(g, 6, CS);
     __syncthreads();
     const uint64_t tiles = 1ull << (g.m_log - 7);
     uint64_t t = blockIdx.x;
@@ -566,14 +594,8 @@ __global__ void __launch_bounds__(256) k_skinny(GemmArgs g) {
             const uint64_t cb = cbase + deposit((uint64_t)nb << 4, g.cpn, 4, g.n_log);
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                uint64_t off_hi = 0;
-                int src_hi = 0;
-                for (int i = 6; i < g.ep_n; ++i)
-                    if ((j >> (i - 6)) & 1) {
-                        off_hi |= 1ull << g.ep_pos[i];
-                        const int sb = g.ep_src[i];
-                        src_hi += sb < 32 ? CS << sb : 1 << (sb - 32);
-                    }
+                const uint64_t off_hi = eh.off(j);
+                const int src_hi = eh.from(j);
                 C[cb + (off_lo | off_hi)] = Cs[w][src_lo + src_hi];
             }
             __syncthreads();
@@ -677,6 +699,7 @@ __global__ void __launch_bounds__(256) k_panel(GemmArgs g) {
             const int sb = g.ep_src[i];
             src_lo += sb < 32 ? CS << sb : 1 << (sb - 32);
         }
+    const EpHigh eh = ep_high(g, 8, CS);
     float mx = 0.f;
     const uint64_t cbase = deposit(ti.m0, g.cpm, 7, g.m_log) + deposit(ti.beta, g.cpb, 0, g.b_log);
     float* cs = reinterpret_cast<float*>(Cs);
@@ -694,14 +717,8 @@ __global__ void __launch_bounds__(256) k_panel(GemmArgs g) {
         const uint64_t cb = cbase + deposit(ti.n0 + ((uint64_t)nb << 4), g.cpn, 4, g.n_log);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            uint64_t off_hi = 0;
-            int src_hi = 0;
-            for (int i = 8; i < g.ep_n; ++i)
-                if ((j >> (i - 8)) & 1) {
-                    off_hi |= 1ull << g.ep_pos[i];
-                    const int sb = g.ep_src[i];
-                    src_hi += sb < 32 ? CS << sb : 1 << (sb - 32);
-                }
+            const uint64_t off_hi = eh.off(j);
+            const int src_hi = eh.from(j);
             C[cb + (off_lo | off_hi)] = Cs[src_lo + src_hi];
         }
     }
@@ -797,6 +814,7 @@ __global__ void __launch_bounds__(256) k_panel3(GemmArgs g) {
             const int sb = g.ep_src[i];
             src_lo += sb < 32 ? CS << sb : 1 << (sb - 32);
         }
+    const EpHigh eh = ep_high(g, 8, CS);
     float mx = 0.f;
     const uint64_t cbase = deposit(ti.m0, g.cpm, 7, g.m_log) + deposit(ti.beta, g.cpb, 0, g.b_log);
     float2* C = reinterpret_cast<float2*>(g.C);
@@ -817,14 +835,8 @@ __global__ void __launch_bounds__(256) k_panel3(GemmArgs g) {
         const uint64_t cb = cbase + deposit(ti.n0 + ((uint64_t)sl << 4), g.cpn, 4, g.n_log);
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) {
-            uint64_t off_hi = 0;
-            int src_hi = 0;
-            for (int i = 8; i < g.ep_n; ++i)
-                if ((jj >> (i - 8)) & 1) {
-                    off_hi |= 1ull << g.ep_pos[i];
-                    const int sb = g.ep_src[i];
-                    src_hi += sb < 32 ? CS << sb : 1 << (sb - 32);
-                }
+            const uint64_t off_hi = eh.off(jj);
+            const int src_hi = eh.from(jj);
             C[cb + (off_lo | off_hi)] = Cs[src_lo + src_hi];
         }
     }
@@ -867,6 +879,22 @@ __device__ __forceinline__ void split_pack(float2 v, float s, uint32_t& hi, uint
 // (re, -im) pairs, odd real column (im part) takes (im, re) pairs.
 __device__ __forceinline__ uint32_t bexp(uint32_t w, int odd) {
     return odd ? ((w >> 16) | (w << 16)) : (w ^ 0x80000000u);
+}
+
+// Split for the panels: v is scaled by s, which in split mode carries an
+// extra 2^11, so hi = fp16(x) is 2^11 times the FP16 head of the operand and
+// lo = fp16(x - hi) its remainder at the same scale (x - hi is exact in
+// FP32).  The products hi_a hi_b + hi_a lo_b + lo_a hi_b then carry 2^22.
+template <int MODE>
+__device__ __forceinline__ void split_pack11(float2 v, float s, uint32_t& hi, uint32_t& lo) {
+    if constexpr (MODE == LP_SPLIT_FP16) {
+        const float xr = v.x * s, xi = v.y * s;
+        const half2v h = __builtin_amdgcn_cvt_pkrtz(xr, xi);
+        hi = __builtin_bit_cast(uint32_t, h);
+        lo = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(xr - (float)h.x, xi - (float)h.y));
+    } else {
+        split_pack<MODE>(v, s, hi, lo);
+    }
 }
 
 __device__ __forceinline__ int scale_exp(const float* mx) {
@@ -1042,11 +1070,11 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
 // (r, h) supplies eight halves = four packed (re, im) words of complex k
 // 4 h .. 4 h + 3 of an 8-k step, for row r; B' words are staged in LDS k-fastest
 // (rows of real columns: (re, -im) for column 2n, (im, re) for 2n+1).  Split
-// mode keeps one accumulator for 2^11 a b = (2^11 hi_a) hi_b + hi_a lo_b +
-// lo_a hi_b (2^11 hi_a is exact in FP16: |hi_a| < 1 after scaling); the
-// result is acc * 2^(ea+eb-11).
+// mode keeps one accumulator for 2^22 a b = hi_a hi_b + hi_a lo_b + lo_a hi_b
+// with both operands split at 2^11 (split_pack11; |x| < 2^11 after scaling,
+// well inside FP16); the result is acc * 2^(ea+eb-22).
 template <int KC, int NB, int MODE, bool PRE, bool NT>
-__global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB >= 8 ? 2 : 1))) k_panel_lp(GemmArgs g) {
     constexpr int N = 16 * NB;
     constexpr int NR = 2 * N;
     constexpr bool SPLIT = MODE == LP_SPLIT_FP16;
@@ -1068,7 +1096,7 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
     const float2* B = reinterpret_cast<const float2*>(g.B) + slice_offset(g.d_slice, g.sb_n, g.sb_bit, g.sb_pos) +
                       (ti.beta << g.n_log) + ti.n0;
     const int ea = scale_exp(g.amax), eb = scale_exp(g.bmax);
-    const float sa = ldexpf(1.f, -ea), sb = ldexpf(1.f, -eb);
+    const float sa = ldexpf(1.f, -ea + (SPLIT ? 11 : 0)), sb = ldexpf(1.f, -eb + (SPLIT ? 11 : 0));
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int r = lane & 31, h = lane >> 5;
     const uint64_t K = 1ull << g.k_log;
@@ -1105,11 +1133,22 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
                 }
         }
     };
+    // B chunk element of thread slot i: each wave instruction covers 4
+    // consecutive columns by 16 k, so the word stores into the k-fastest
+    // rows below (row stride KC + 4 words) fall into 32 distinct banks per
+    // half-wave (a column-fastest walk would put 8 lanes on each bank)
+    auto b_elem = [&](int i, int& kk, int& nn) {
+        constexpr int KQ = KC / 16;
+        const int l = tid & 63, q = (tid >> 6) + 4 * i;
+        kk = (l >> 2) + 16 * (q % KQ);
+        nn = (l & 3) + 4 * (q / KQ);
+    };
     auto load_b = [&](uint64_t k0) {
 #pragma unroll
         for (int i = 0; i < PBN; ++i) {
-            const int e = tid + 256 * i;
-            bb[i] = B[(k0 + e / N) * sBk + (e % N)];
+            int kk, nn;
+            b_elem(i, kk, nn);
+            bb[i] = B[(k0 + kk) * sBk + nn];
         }
     };
     floatx16 acc[NB];
@@ -1123,9 +1162,10 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < PBN; ++i) {
-            const int e = tid + 256 * i, kk = e / N, nn = e % N;
+            int kk, nn;
+            b_elem(i, kk, nn);
             uint32_t hi, lo;
-            split_pack<MODE>(bb[i], sb, hi, lo);
+            split_pack11<MODE>(bb[i], sb, hi, lo);
             Bw[0][(2 * nn) * RS + kk] = bexp(hi, 0);
             Bw[0][(2 * nn + 1) * RS + kk] = bexp(hi, 1);
             if constexpr (SPLIT) {
@@ -1147,12 +1187,11 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
             } else {
                 uint32_t hw[4], lw[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) split_pack<MODE>(av[s][i], sa, hw[i], lw[i]);
+                for (int i = 0; i < 4; ++i) split_pack11<MODE>(av[s][i], sa, hw[i], lw[i]);
                 ah = uint4{hw[0], hw[1], hw[2], hw[3]};
                 al = uint4{lw[0], lw[1], lw[2], lw[3]};
             }
-            half8 ah8 = __builtin_bit_cast(half8, ah);
-            if constexpr (SPLIT) ah8 = ah8 * (_Float16)2048.f;   // exact: a power-of-two scaling
+            const half8 ah8 = __builtin_bit_cast(half8, ah);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int o = (nb * 32 + r) * RS + 8 * s + 4 * h;
@@ -1185,7 +1224,7 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
                 for (int i = 0; i < 4; ++i) av[s][i] = an[s][i];
         }
     }
-    const float sc = ldexpf(1.f, ea + eb - (SPLIT ? 11 : 0));
+    const float sc = ldexpf(1.f, ea + eb - (SPLIT ? 22 : 0));
     uint64_t off_lo = 0;
     int src_lo = 0;
     for (int i = 0; i < 8; ++i)
@@ -1194,6 +1233,7 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
             const int sbt = g.ep_src[i];
             src_lo += sbt < 32 ? CS << sbt : 1 << (sbt - 32);
         }
+    const EpHigh eh = ep_high(g, 8, CS);
     float mx = 0.f;
     const uint64_t cbase = deposit(ti.m0, g.cpm, 7, g.m_log) + deposit(ti.beta, g.cpb, 0, g.b_log);
     float* cs = reinterpret_cast<float*>(Cs);
@@ -1212,14 +1252,8 @@ __global__ void __launch_bounds__(256) k_panel_lp(GemmArgs g) {
         const uint64_t cb = cbase + deposit(ti.n0 + ((uint64_t)nb << 4), g.cpn, 4, g.n_log);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            uint64_t off_hi = 0;
-            int src_hi = 0;
-            for (int i = 8; i < g.ep_n; ++i)
-                if ((j >> (i - 8)) & 1) {
-                    off_hi |= 1ull << g.ep_pos[i];
-                    const int sbt = g.ep_src[i];
-                    src_hi += sbt < 32 ? CS << sbt : 1 << (sbt - 32);
-                }
+            const uint64_t off_hi = eh.off(j);
+            const int src_hi = eh.from(j);
             C[cb + (off_lo | off_hi)] = Cs[src_lo + src_hi];
         }
     }
@@ -1235,13 +1269,13 @@ __global__ void __launch_bounds__(256) k_lp_convert_a(GemmArgs g, uint32_t* hi, 
     const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos);
     const uint64_t rows = 1ull << (g.m_log + g.b_log);
     const uint64_t n = rows << (g.k_log - 2);
-    const float sc = ldexpf(1.f, -scale_exp(g.amax));
+    const float sc = ldexpf(1.f, -scale_exp(g.amax) + (MODE == LP_SPLIT_FP16 ? 11 : 0));
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     for (uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += stride) {
         const uint64_t q = t / rows, row = t % rows;
         uint32_t h[4], l[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) split_pack<MODE>(A[(4 * q + i) * rows + row], sc, h[i], l[i]);
+        for (int i = 0; i < 4; ++i) split_pack11<MODE>(A[(4 * q + i) * rows + row], sc, h[i], l[i]);
         reinterpret_cast<uint4*>(hi)[t] = uint4{h[0], h[1], h[2], h[3]};
         if constexpr (MODE == LP_SPLIT_FP16) reinterpret_cast<uint4*>(lo)[t] = uint4{l[0], l[1], l[2], l[3]};
     }
@@ -1515,6 +1549,10 @@ static hipError_t launch_lp(int tile, const GemmArgs& g, dim3 grid, hipStream_t 
 
 template <int MODE, bool PRE, bool NT>
 static hipError_t launch_panel_lp_t(int tile, const GemmArgs& g, dim3 grid, hipStream_t s) {
+    if (tile & 64) {   // KC = 16 only (KC = 32 spills at two waves per SIMD)
+        hipLaunchKernelGGL((k_panel_lp<16, 8, MODE, PRE, NT>), grid, dim3(256), 0, s, g);
+        return hipGetLastError();
+    }
     switch (tile & 3) {
         case 0: hipLaunchKernelGGL((k_panel_lp<32, 4, MODE, PRE, NT>), grid, dim3(256), 0, s, g); break;
         case 1: hipLaunchKernelGGL((k_panel_lp<16, 4, MODE, PRE, NT>), grid, dim3(256), 0, s, g); break;
@@ -1526,9 +1564,9 @@ static hipError_t launch_panel_lp_t(int tile, const GemmArgs& g, dim3 grid, hipS
 
 hipError_t launch_panel_lp(int mode, int tile, const GemmArgs& g, uint32_t* conv, hipStream_t s) {
     // tile bits as in launch_panel; bit 4 (non-temporal A loads) applies to
-    // A split in registers (conv = null) only
-    const int kc_log = (tile & 1) ? 4 : 5, nb_log = (tile & 2) ? 1 : 2;
-    if (tile < 0 || (tile & ~19) || (conv && (tile & 16)) || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) ||
+    // A split in registers (conv = null) only; bit 6: NB = 8 (KC = 16)
+    const int kc_log = (tile & 1) ? 4 : 5, nb_log = (tile & 64) ? 3 : ((tile & 2) ? 1 : 2);
+    if (tile < 0 || (tile & ~83) || ((tile & 64) && (tile & 3) != 1) || (conv && (tile & 16)) || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) ||
         g.k_log < kc_log || g.ep_n != 11 || g.split_log != 0 || (mode != LP_SPLIT_FP16 && mode != LP_BF16))
         return hipErrorInvalidValue;
     const dim3 grid = grid_for(tile_blocks(g));

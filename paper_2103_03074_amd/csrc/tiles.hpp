@@ -40,10 +40,12 @@ inline bool skinny_ok(int m, int n, int k, int b, tn_precision prec) {
 // in registers instead of reading planes split by a separate pass, bit 4 ->
 // A loaded with non-temporal loads (FP32 panels and A split in registers),
 // bit 5 -> complex64 panel with three real products per complex
-// multiply-add (Gauss's form) instead of four.
+// multiply-add (Gauss's form) instead of four, bit 6 -> NB = 8 (mixed-form
+// GEMM only, with KC = 16: 128 complex columns per block, so each A element
+// is loaded and split once per 128 columns instead of once per 32 or 64).
 constexpr int kNumPanelTiles = 4;
 inline int panel_kc_log(int tile) { return (tile & 1) ? 4 : 5; }
-inline int panel_tn_log(int tile) { return (tile & 2) ? 5 : 6; }
+inline int panel_tn_log(int tile) { return (tile & 64) ? 7 : ((tile & 2) ? 5 : 6); }
 inline bool panel_fp32(int tile, tn_precision prec) { return prec == TN_C64 || (tile & 4); }
 inline bool panel_ok(int m, int n, int k, int b, tn_precision prec, int tile) {
     return mfma_capable(prec) && m >= 7 && n >= panel_tn_log(tile) && k >= panel_kc_log(tile) &&
