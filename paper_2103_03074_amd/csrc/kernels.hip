@@ -617,7 +617,8 @@ __global__ void __launch_bounds__(256) k_skinny(GemmArgs g) {
 // (tile bits m0..m6, n0..n3 in the epilogue decode).  Tiles are visited in
 // the XCD-aware order of tile_index (tm = 7, tn = 4 + log2 NB).
 template <int KC, int NB, bool NT>
-__global__ void __launch_bounds__(256) k_panel(GemmArgs g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KC == 16 ? (NB >= 4 ? 3 : 4) : 1)))
+k_panel(GemmArgs g) {
     constexpr int N = 16 * NB;
     constexpr int KP = KC / 2;
     constexpr int CS = 17;
@@ -735,7 +736,8 @@ __global__ void __launch_bounds__(256) k_panel(GemmArgs g) {
 // each output is bounded by the same products' magnitudes as the four-term
 // form, up to a factor of about two.
 template <int KC, int NB, bool NT>
-__global__ void __launch_bounds__(256) k_panel3(GemmArgs g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KC == 16 ? (NB >= 4 ? 3 : 4) : 1)))
+k_panel3(GemmArgs g) {
     constexpr int N = 16 * NB;
     constexpr int NT3 = N / 32;             // 32-column MFMA tiles
     constexpr int KP = KC / 2;
@@ -1074,7 +1076,8 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
 // with both operands split at 2^11 (split_pack11; |x| < 2^11 after scaling,
 // well inside FP16); the result is acc * 2^(ea+eb-22).
 template <int KC, int NB, int MODE, bool PRE, bool NT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB >= 8 ? 2 : 1))) k_panel_lp(GemmArgs g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB >= 8 ? 2 : (NB == 2 ? (KC == 16 ? 4 : 3) : 1))))
+k_panel_lp(GemmArgs g) {
     constexpr int N = 16 * NB;
     constexpr int NR = 2 * N;
     constexpr bool SPLIT = MODE == LP_SPLIT_FP16;
