@@ -743,7 +743,8 @@ k_panel3(GemmArgs g) {
     constexpr int KP = KC / 2;
     constexpr int CS = 17;
     constexpr int PBN = KC * N / 256;
-    constexpr int SMEM = KC * N > 128 * CS ? KC * N : 128 * CS;
+    // the B chunks and the two output slabs of a 32-column tile share LDS
+    constexpr int SMEM = KC * N > 256 * CS ? KC * N : 256 * CS;
     __shared__ __attribute__((aligned(16))) float2 smem[SMEM];
     float2* const Bs = smem;
     float2* const Cs = smem;
@@ -821,25 +822,27 @@ k_panel3(GemmArgs g) {
     const uint64_t cbase = deposit(ti.m0, g.cpm, 7, g.m_log) + deposit(ti.beta, g.cpb, 0, g.b_log);
     float2* C = reinterpret_cast<float2*>(g.C);
 #pragma unroll
-    for (int sl = 0; sl < 2 * NT3; ++sl) {
-        const int j = sl >> 1, hf = sl & 1;
+    for (int j = 0; j < NT3; ++j) {
+        // both 16-column slabs of the tile at once: lane column r goes to
+        // slab r >> 4
         __syncthreads();
-        if ((r >> 4) == hf) {
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int row = w * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-                const float2 c = make_float2(t1[j][v] - t3[j][v], t1[j][v] + t2[j][v]);
-                Cs[row * CS + (r & 15)] = c;
-                mx = fmaxf(mx, fmaxf(fabsf(c.x), fabsf(c.y)));
-            }
+        for (int v = 0; v < 16; ++v) {
+            const int row = w * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+            const float2 c = make_float2(t1[j][v] - t3[j][v], t1[j][v] + t2[j][v]);
+            Cs[(r >> 4) * 128 * CS + row * CS + (r & 15)] = c;
+            mx = fmaxf(mx, fmaxf(fabsf(c.x), fabsf(c.y)));
         }
         __syncthreads();
-        const uint64_t cb = cbase + deposit(ti.n0 + ((uint64_t)sl << 4), g.cpn, 4, g.n_log);
 #pragma unroll
-        for (int jj = 0; jj < 8; ++jj) {
-            const uint64_t off_hi = eh.off(jj);
-            const int src_hi = eh.from(jj);
-            C[cb + (off_lo | off_hi)] = Cs[src_lo + src_hi];
+        for (int hf = 0; hf < 2; ++hf) {
+            const uint64_t cb = cbase + deposit(ti.n0 + ((uint64_t)(2 * j + hf) << 4), g.cpn, 4, g.n_log);
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                const uint64_t off_hi = eh.off(jj);
+                const int src_hi = eh.from(jj);
+                C[cb + (off_lo | off_hi)] = Cs[hf * 128 * CS + src_lo + src_hi];
+            }
         }
     }
     if (g.cmax) tile_max_atomic(mx, g.cmax);

@@ -425,6 +425,44 @@ def test_c3_every_kernel_configuration_of_dense_steps(prec):
         p.set_step_kernel(step, *orig)
 
 
+@pytest.mark.parametrize("prec", ["split_fp16", "bf16"])
+def test_c2_low_precision_kernel_forced_onto_invariant_consumer(prec):
+    """A low-precision GEMM scales its operands by the producers' recorded
+    maxima.  The invariant tensors are produced once, at the first call, by
+    whatever kernel their consumer had then; forcing a low-precision MFMA or
+    panel kernel afterwards onto a slice-dependent step that started on a
+    VALU or skinny kernel and reads an invariant tensor must still find that
+    tensor's maximum (else small entries would underflow in FP16).  One slice
+    against the oracle per forced configuration."""
+    w = rqc.workload("c2_5x5_m16")
+    p = _plan(w, n_slice_edges=8, restarts=4, prec=prec, seed=0)
+    ex = p.export()
+    inv = {st["node"] for st in ex["steps"] if st["invariant"]}
+    picks = []
+    for i, st in enumerate(ex["steps"]):
+        if st["invariant"] or st["kernel"] in (1, 5) or not ({st["a"], st["b"]} & inv):
+            continue
+        lp = [(k, t) for k, t in p.step_candidates(i) if k == 1 or (k == 5 and not t & 4)]
+        if lp:
+            picks.append((i, lp))
+    assert picks, "no slice-dependent non-MFMA step reads an invariant tensor"
+    sliced = [tuple(e) for e in ex["sliced"]]
+    tree = list(zip(ex["lhs"], ex["rhs"]))
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    j = 37
+    ref = nw.contract(nw.slice_network(net, sliced, nw.slice_values(sliced, j)), tree)
+    _run(p, (0, 1))   # the first call produces the invariant tensors under the original kernels
+    for step, lp in picks[:2]:
+        st = ex["steps"][step]
+        orig = (st["kernel"], st["tile"])
+        for kernel, tile in lp:
+            _say("c2", prec, "invariant consumer", step, (st["m"], st["n"], st["k"], st["batch"]), "from", orig,
+                 "to", kernel, tile)
+            p.set_step_kernel(step, kernel, tile)
+            _check(_run(p, (j, j + 1)), ref, MIXED_TOL[prec], step, kernel, tile)
+        p.set_step_kernel(step, *orig)
+
+
 def test_autotune_keeps_results_and_caches(tmp_path):
     torch = _torch()
     from paper_2103_03074_amd import runtime
