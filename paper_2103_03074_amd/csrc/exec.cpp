@@ -189,8 +189,10 @@ std::string launch_step(const Plan& p, const DeviceState& d, const Step& st, con
             e = launch_panel_lp(mode, lt, g, conv, s);
         } else {
             const bool three = st.tile & 32;
-            if (name) *name = std::string(three ? "k_panel3<" : "k_panel<") + kcnb + (nt ? "true>" : "false>");
-            e = launch_panel(st.tile & 51, g, s);
+            if (name)
+                *name = (st.tile & 128) ? std::string("k_panel3d<") + (tnl == 6 ? "4>" : "2>")
+                                        : std::string(three ? "k_panel3<" : "k_panel<") + kcnb + (nt ? "true>" : "false>");
+            e = launch_panel(st.tile & 179, g, s);
         }
         if (e != hipSuccess) return std::string("panel launch: ") + hipGetErrorString(e);
         return "";
@@ -566,6 +568,7 @@ std::vector<Candidate> candidates(const Step& st, tn_precision prec) {
                 c.push_back({K_PANEL, t | 16, 0});        // non-temporal A loads
                 c.push_back({K_PANEL, t | 32, 0});        // three real products per complex product
                 c.push_back({K_PANEL, t | 32 | 16, 0});
+                if (t & 1) c.push_back({K_PANEL, t | 32 | 128, 0});   // A staged in LDS by direct loads
             } else {
                 c.push_back({K_PANEL, t | 4, 0});        // FP32 panel in a mixed form
                 c.push_back({K_PANEL, t | 4 | 16, 0});

@@ -848,6 +848,128 @@ k_panel3(GemmArgs g) {
     if (g.cmax) tile_max_atomic(mx, g.cmax);
 }
 
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+// k_panel3 with the A chunks staged in LDS by direct global-to-LDS loads
+// (global_load_lds_dwordx4: each wave instruction moves one k row of the
+// block's 128 rows, 1 KB, without passing through registers), double
+// buffered in two separate LDS arrays so the compiler orders each read only
+// after the loads into its own buffer; the next chunk's A and B loads are in
+// flight while the current chunk is multiplied.  K chunks of 16.  The two
+// A buffers double as the epilogue's slab buffers (128 rows x 17 complex).
+template <int NB>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB >= 4 ? 3 : 4)))
+k_panel3d(GemmArgs g) {
+    constexpr int KC = 16, N = 16 * NB, NT3 = N / 32, KP = KC / 2, CS = 17, PBN = KC * N / 256;
+    constexpr int AS = 128 * CS;             // a stage holds KC x 128 complex (and a slab when staging C)
+    __shared__ __attribute__((aligned(16))) float2 As0[AS];
+    __shared__ __attribute__((aligned(16))) float2 As1[AS];
+    __shared__ __attribute__((aligned(16))) float2 Bs[KC * N];
+    const TileIndex ti = tile_index(g);
+    const uint64_t sAk = 1ull << (g.m_log + g.b_log), sBk = 1ull << (g.n_log + g.b_log);
+    const float2* A = reinterpret_cast<const float2*>(g.A) + slice_offset(g.d_slice, g.sa_n, g.sa_bit, g.sa_pos) +
+                      (ti.beta << g.m_log) + ti.m0;
+    const float2* B = reinterpret_cast<const float2*>(g.B) + slice_offset(g.d_slice, g.sb_n, g.sb_bit, g.sb_pos) +
+                      (ti.beta << g.n_log) + ti.n0;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int r = lane & 31, h = lane >> 5;
+    const uint64_t K = 1ull << g.k_log;
+    // wave w moves k rows 4w .. 4w+3 of a chunk; lane l the rows 2l, 2l+1
+    auto load_a = [&](float2* stage, uint64_t k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int kk = 4 * w + i;
+            __builtin_amdgcn_global_load_lds(static_cast<const void*>(A + (k0 + kk) * sAk + 2 * lane),
+                                             (lds_void_ptr)(stage + kk * 128), 16, 0, 0);
+        }
+    };
+    float2 bb[PBN];
+    auto load_b = [&](uint64_t k0) {
+#pragma unroll
+        for (int i = 0; i < PBN; ++i) {
+            const int e = tid + 256 * i;
+            bb[i] = B[(k0 + e / N) * sBk + (e % N)];
+        }
+    };
+    floatx16 t1[NT3], t2[NT3], t3[NT3];
+#pragma unroll
+    for (int j = 0; j < NT3; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) t1[j][v] = t2[j][v] = t3[j][v] = 0.f;
+    // Workgroup barrier after this wave's LDS stores have completed, without
+    // the wait for all outstanding global loads that __syncthreads() implies
+    // (it would also wait for the next chunk's loads, already in flight)
+    auto lds_barrier = [] { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
+    auto chunk = [&](const float2* cur, float2* nxt, uint64_t k0) {
+        lds_barrier();   // the previous chunk's readers of Bs and of nxt are done
+#pragma unroll
+        for (int i = 0; i < PBN; ++i) Bs[tid + 256 * i] = bb[i];
+        if (k0 + KC < K) {
+            load_a(nxt, k0 + KC);
+            load_b(k0 + KC);
+            // this wave's loads of the current chunk have landed (loads
+            // complete in order); the barrier makes every wave's visible
+            asm volatile("s_waitcnt vmcnt(%0)" ::"n"(4 + PBN) : "memory");
+        } else {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        }
+        lds_barrier();
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+            const float2 a = cur[(2 * p + h) * 128 + w * 32 + r];
+            const float a1 = a.x + a.y;
+#pragma unroll
+            for (int j = 0; j < NT3; ++j) {
+                const float2 b = Bs[(2 * p + h) * N + j * 32 + r];
+                t1[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b.x, t1[j], 0, 0, 0);
+                t2[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y - b.x, t2[j], 0, 0, 0);
+                t3[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x + b.y, t3[j], 0, 0, 0);
+            }
+        }
+    };
+    load_a(As0, 0);
+    load_b(0);
+    for (uint64_t k0 = 0; k0 < K; k0 += 2 * KC) {
+        chunk(As0, As1, k0);
+        if (k0 + KC < K) chunk(As1, As0, k0 + KC);
+    }
+    // epilogue: both 16-column slabs of a 32-column tile at once, slab hf in
+    // the A buffer hf
+    uint64_t off_lo = 0;
+    int src_lo = 0;
+    for (int i = 0; i < 8; ++i)
+        if ((tid >> i) & 1) {
+            off_lo |= 1ull << g.ep_pos[i];
+            const int sb = g.ep_src[i];
+            src_lo += sb < 32 ? CS << sb : 1 << (sb - 32);
+        }
+    const EpHigh eh = ep_high(g, 8, CS);
+    float mx = 0.f;
+    const uint64_t cbase = deposit(ti.m0, g.cpm, 7, g.m_log) + deposit(ti.beta, g.cpb, 0, g.b_log);
+    float2* C = reinterpret_cast<float2*>(g.C);
+#pragma unroll
+    for (int j = 0; j < NT3; ++j) {
+        __syncthreads();
+        float2* slab = (r >> 4) ? As1 : As0;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = w * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+            const float2 c = make_float2(t1[j][v] - t3[j][v], t1[j][v] + t2[j][v]);
+            slab[row * CS + (r & 15)] = c;
+            mx = fmaxf(mx, fmaxf(fabsf(c.x), fabsf(c.y)));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            const float2* src = hf ? As1 : As0;
+            const uint64_t cb = cbase + deposit(ti.n0 + ((uint64_t)(2 * j + hf) << 4), g.cpn, 4, g.n_log);
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) C[cb + (off_lo | eh.off(jj))] = src[src_lo + eh.from(jj)];
+        }
+    }
+    if (g.cmax) tile_max_atomic(mx, g.cmax);
+}
+
 // ------------------------------------------------- low-precision MFMA
 
 constexpr int kRowPad = 36;   // words per staged row: 32 k + 4 (bank spread, 16-byte aligned)
@@ -1197,24 +1319,32 @@ k_panel_lp(GemmArgs g) {
                 ah = uint4{hw[0], hw[1], hw[2], hw[3]};
                 al = uint4{lw[0], lw[1], lw[2], lw[3]};
             }
-            const half8 ah8 = __builtin_bit_cast(half8, ah);
+            const half8 ah8 = __builtin_bit_cast(half8, ah), al8 = __builtin_bit_cast(half8, al);
+            // two accumulation chains at a time with their B' fragments read
+            // together: consecutive MFMAs are independent, and one LDS wait
+            // covers the pair's reads
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const int o = (nb * 32 + r) * RS + 8 * s + 4 * h;
-                const uint4 bh = *reinterpret_cast<const uint4*>(&Bw[0][o]);
+            for (int nb = 0; nb < NB; nb += 2) {
+                const int o0 = (nb * 32 + r) * RS + 8 * s + 4 * h, o1 = o0 + 32 * RS;
+                const uint4 bh0 = *reinterpret_cast<const uint4*>(&Bw[0][o0]);
+                const uint4 bh1 = *reinterpret_cast<const uint4*>(&Bw[0][o1]);
                 if constexpr (MODE == LP_BF16) {
-                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah),
-                                                                      __builtin_bit_cast(bf16x8, bh), acc[nb], 0, 0, 0);
+                    const bf16x8 ab = __builtin_bit_cast(bf16x8, ah);
+                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, __builtin_bit_cast(bf16x8, bh0), acc[nb], 0, 0, 0);
+                    acc[nb + 1] =
+                        __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, __builtin_bit_cast(bf16x8, bh1), acc[nb + 1], 0, 0, 0);
                 } else {
+                    const half8 h0 = __builtin_bit_cast(half8, bh0), h1 = __builtin_bit_cast(half8, bh1);
                     if constexpr (SPLIT) {
-                        const uint4 bl = *reinterpret_cast<const uint4*>(&Bw[PL - 1][o]);
-                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, ah),
-                                                                         __builtin_bit_cast(half8, bl), acc[nb], 0, 0, 0);
-                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, al),
-                                                                         __builtin_bit_cast(half8, bh), acc[nb], 0, 0, 0);
+                        const half8 l0 = __builtin_bit_cast(half8, *reinterpret_cast<const uint4*>(&Bw[PL - 1][o0]));
+                        const half8 l1 = __builtin_bit_cast(half8, *reinterpret_cast<const uint4*>(&Bw[PL - 1][o1]));
+                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, l0, acc[nb], 0, 0, 0);
+                        acc[nb + 1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, l1, acc[nb + 1], 0, 0, 0);
+                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al8, h0, acc[nb], 0, 0, 0);
+                        acc[nb + 1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al8, h1, acc[nb + 1], 0, 0, 0);
                     }
-                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, __builtin_bit_cast(half8, bh), acc[nb],
-                                                                     0, 0, 0);
+                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, h0, acc[nb], 0, 0, 0);
+                    acc[nb + 1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, h1, acc[nb + 1], 0, 0, 0);
                 }
             }
         }
@@ -1516,13 +1646,17 @@ static void launch_panel_t(int tile, const GemmArgs& g, dim3 grid, hipStream_t s
 hipError_t launch_panel(int tile, const GemmArgs& g, hipStream_t s) {
     // tile: bit 0 -> KC = 16 (else 32), bit 1 -> NB = 2 (else 4), bit 4 ->
     // non-temporal A loads, bit 5 -> three real products per complex
-    // multiply-add (k_panel3)
+    // multiply-add (k_panel3), bit 7 -> k_panel3 with A staged in LDS by
+    // direct loads (KC = 16, no bit 4)
     const int kc_log = (tile & 1) ? 4 : 5, nb_log = (tile & 2) ? 1 : 2;
-    if (tile < 0 || (tile & ~51) || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) || g.k_log < kc_log ||
-        g.ep_n != 11 || g.split_log != 0)
+    if (tile < 0 || (tile & ~179) || g.tm != 7 || g.tn != 4 + nb_log || !tile_fits(g) || g.k_log < kc_log ||
+        g.ep_n != 11 || g.split_log != 0 || ((tile & 128) && (tile & 49) != 33))
         return hipErrorInvalidValue;
     const dim3 grid = grid_for(tile_blocks(g));
-    if (tile & 32) {
+    if (tile & 128) {
+        if (tile & 2) hipLaunchKernelGGL((k_panel3d<2>), grid, dim3(256), 0, s, g);
+        else hipLaunchKernelGGL((k_panel3d<4>), grid, dim3(256), 0, s, g);
+    } else if (tile & 32) {
         if (tile & 16) launch_panel3_t<true>(tile, g, grid, s);
         else launch_panel3_t<false>(tile, g, grid, s);
     } else {
