@@ -1396,7 +1396,6 @@ k_panel_lp(GemmArgs g) {
     if (g.cmax) tile_max_atomic(mx, g.cmax);
 }
 
-
 // Split a complex64 A operand ([K | batch | M], scaled by 2^-e from the
 // producer's max) into word planes laid out [K/4][batch, M][4]: the four k of
 // one row that a lane of k_panel_lp needs are one 16-byte load.
