@@ -1201,7 +1201,7 @@ __global__ void __launch_bounds__(256) k_mfma_lp(GemmArgs g) {
 // with both operands split at 2^11 (split_pack11; |x| < 2^11 after scaling,
 // well inside FP16); the result is acc * 2^(ea+eb-22).
 template <int KC, int NB, int MODE, bool PRE, bool NT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB >= 8 ? 2 : (NB == 2 ? (KC == 16 ? 4 : 3) : 1))))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB >= 8 ? 2 : (NB == 2 ? (KC == 16 ? 4 : 3) : (KC == 16 ? 3 : 1)))))
 k_panel_lp(GemmArgs g) {
     constexpr int N = 16 * NB;
     constexpr int NR = 2 * N;
