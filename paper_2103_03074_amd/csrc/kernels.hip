@@ -1320,31 +1320,37 @@ k_panel_lp(GemmArgs g) {
                 al = uint4{lw[0], lw[1], lw[2], lw[3]};
             }
             const half8 ah8 = __builtin_bit_cast(half8, ah), al8 = __builtin_bit_cast(half8, al);
-            // two accumulation chains at a time with their B' fragments read
-            // together: consecutive MFMAs are independent, and one LDS wait
-            // covers the pair's reads
+            // G accumulation chains at a time with their B' fragments read
+            // together: each chain's next MFMA is G issues later, and one
+            // LDS wait covers the group's reads
+            constexpr int G = NB >= 8 ? 4 : 2;
 #pragma unroll
-            for (int nb = 0; nb < NB; nb += 2) {
-                const int o0 = (nb * 32 + r) * RS + 8 * s + 4 * h, o1 = o0 + 32 * RS;
-                const uint4 bh0 = *reinterpret_cast<const uint4*>(&Bw[0][o0]);
-                const uint4 bh1 = *reinterpret_cast<const uint4*>(&Bw[0][o1]);
+            for (int nb = 0; nb < NB; nb += G) {
+                half8 bh[G], bl[SPLIT ? G : 1];
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    const int o = ((nb + q) * 32 + r) * RS + 8 * s + 4 * h;
+                    bh[q] = __builtin_bit_cast(half8, *reinterpret_cast<const uint4*>(&Bw[0][o]));
+                    if constexpr (SPLIT) bl[q] = __builtin_bit_cast(half8, *reinterpret_cast<const uint4*>(&Bw[PL - 1][o]));
+                }
                 if constexpr (MODE == LP_BF16) {
                     const bf16x8 ab = __builtin_bit_cast(bf16x8, ah);
-                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, __builtin_bit_cast(bf16x8, bh0), acc[nb], 0, 0, 0);
-                    acc[nb + 1] =
-                        __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, __builtin_bit_cast(bf16x8, bh1), acc[nb + 1], 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < G; ++q)
+                        acc[nb + q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, __builtin_bit_cast(bf16x8, bh[q]),
+                                                                              acc[nb + q], 0, 0, 0);
                 } else {
-                    const half8 h0 = __builtin_bit_cast(half8, bh0), h1 = __builtin_bit_cast(half8, bh1);
                     if constexpr (SPLIT) {
-                        const half8 l0 = __builtin_bit_cast(half8, *reinterpret_cast<const uint4*>(&Bw[PL - 1][o0]));
-                        const half8 l1 = __builtin_bit_cast(half8, *reinterpret_cast<const uint4*>(&Bw[PL - 1][o1]));
-                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, l0, acc[nb], 0, 0, 0);
-                        acc[nb + 1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, l1, acc[nb + 1], 0, 0, 0);
-                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al8, h0, acc[nb], 0, 0, 0);
-                        acc[nb + 1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al8, h1, acc[nb + 1], 0, 0, 0);
+#pragma unroll
+                        for (int q = 0; q < G; ++q)
+                            acc[nb + q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, bl[q], acc[nb + q], 0, 0, 0);
+#pragma unroll
+                        for (int q = 0; q < G; ++q)
+                            acc[nb + q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al8, bh[q], acc[nb + q], 0, 0, 0);
                     }
-                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, h0, acc[nb], 0, 0, 0);
-                    acc[nb + 1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, h1, acc[nb + 1], 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < G; ++q)
+                        acc[nb + q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, bh[q], acc[nb + q], 0, 0, 0);
                 }
             }
         }
