@@ -42,7 +42,9 @@ inline bool skinny_ok(int m, int n, int k, int b, tn_precision prec) {
 // bit 5 -> complex64 panel with three real products per complex
 // multiply-add (Gauss's form) instead of four, bit 6 -> NB = 8 (mixed-form
 // GEMM only, with KC = 16: 128 complex columns per block, so each A element
-// is loaded and split once per 128 columns instead of once per 32 or 64).
+// is loaded and split once per 128 columns instead of once per 32 or 64),
+// bit 7 -> the three-product complex64 panel with its A chunks moved into
+// LDS by direct global-to-LDS loads (with bits 0 and 5; k_panel3d).
 constexpr int kNumPanelTiles = 4;
 inline int panel_kc_log(int tile) { return (tile & 1) ? 4 : 5; }
 inline int panel_tn_log(int tile) { return (tile & 64) ? 7 : ((tile & 2) ? 5 : 6); }
