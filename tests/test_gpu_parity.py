@@ -463,6 +463,56 @@ def test_c2_low_precision_kernel_forced_onto_invariant_consumer(prec):
         p.set_step_kernel(step, *orig)
 
 
+# panel variants: k_panel3d (A moved into LDS by direct loads; complex64,
+# tile bit 7) and the 128-column mixed panel (tile bit 6)
+_VARIANTS = {"c64": (161, 163), "split_fp16": (73, 89), "bf16": (73, 89)}
+
+
+def _force_everywhere(p, tiles):
+    """Force the first of `tiles` each step accepts onto every step that
+    accepts one; returns the forced steps."""
+    forced = []
+    for i in range(len(p.export()["steps"])):
+        ok = [t for k, t in p.step_candidates(i) if k == 5 and t in tiles]
+        if ok:
+            p.set_step_kernel(i, 5, ok[0])
+            forced.append(i)
+    return forced
+
+
+def test_c2_direct_load_panel_on_every_eligible_step(c2_state):
+    """k_panel3d forced onto every step of the 25-qubit plan that accepts it
+    (one with batch legs), all 2^8 slices against the state vector."""
+    w, psi = c2_state
+    p = _plan(w, n_slice_edges=8, restarts=4, prec="c64", seed=0)
+    forced = _force_everywhere(p, _VARIANTS["c64"])
+    assert any(p.export()["steps"][i]["batch"] > 0 for i in forced), forced
+    _say("c2 direct-load panel on steps", forced)
+    got = _run(p)
+    ref = sv.amplitudes_from_state(psi, 25, w["open_q"], w["fixed_q"], w["bits"])
+    _check(got, ref, C64_TOL, "c2 k_panel3d", forced)
+
+
+@pytest.mark.parametrize("prec", ["c64", "split_fp16", "bf16"])
+def test_c3_panel_variants_on_every_eligible_step(prec):
+    """The direct-load complex64 panel, or the 128-column mixed panel, forced
+    onto every step of the 40-qubit plan that accepts it at once (batched
+    and slice-selected operands included); one slice against the oracle."""
+    w = rqc.workload("c3_5x8_m16")
+    p = _c3_plan(w, prec=prec)
+    forced = _force_everywhere(p, _VARIANTS[prec])
+    assert len(forced) >= 3, forced
+    ex = p.export()
+    sliced = [tuple(e) for e in ex["sliced"]]
+    tree = list(zip(ex["lhs"], ex["rhs"]))
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    j = int(rqc.sample_slice_ids(16, 1, seed=5)[0])
+    _say("c3", prec, "panel variants on", len(forced), "steps, slice", j)
+    got = _run(p, (j, j + 1))
+    ref = nw.contract(nw.slice_network(net, sliced, nw.slice_values(sliced, j)), tree)
+    _check(got, ref, C64_TOL if prec == "c64" else MIXED_TOL[prec], prec, "forced variants")
+
+
 def test_autotune_keeps_results_and_caches(tmp_path):
     torch = _torch()
     from paper_2103_03074_amd import runtime
