@@ -9,6 +9,9 @@ and 24 fixed qubits, sliced into 2^16 subtasks that run in launch groups of
 One step is a fixed chunk of full launch groups (default 16 groups = 4096
 slices) contracted through tn_contract_slices, which replays the captured
 graph of a launch group; consecutive steps walk through the job's groups.
+The groups of a step run on two concurrent lanes (tn_plan_set_lanes: two
+HIP streams, each with its own workspace, graphs and float64 accumulator,
+the lanes' sums added in lane order at the end of the call).
 The value is TFLOP/s of the executed contraction tree over the timed steps
 (8 real flops per complex multiply-add, Eq. (3) of the paper).  Whole-job
 seconds and amplitudes/s are projected from the step time (all groups plus
@@ -192,6 +195,8 @@ def main():
                     help="launch groups of the untimed per-kernel events pass")
     ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
                     help="eager: the timed steps launch kernel by kernel (for profilers)")
+    ap.add_argument("--lanes", type=int, default=2,
+                    help="concurrent lanes of launch groups (HIP streams) in each contraction call")
     ap.add_argument("--restarts", type=int, default=16)
     ap.add_argument("--batch-log2", type=int, default=-1)
     ap.add_argument("--branch-merge", type=int, default=1,
@@ -243,9 +248,10 @@ def main():
                        n_slice_edges=SLICE_EDGES.get(args.workload, -1), batch_log2=args.batch_log2, seed=0,
                        branch_merge=args.branch_merge)
         t_plan = time.perf_counter() - t0
+        plan.set_lanes(args.lanes)
         s = plan.stats()
         log(f"{prec}: planned in {t_plan:.1f}s: {s['n_slices']} slices, 2^{s['batch_log2']} per launch group, "
-            f"largest tensor 2^{s['max_log2_size']}")
+            f"largest tensor 2^{s['max_log2_size']}, {args.lanes} lanes")
         ws = runtime.workspace(plan)
         acc = runtime.accumulator(plan)
         amps = torch.empty(2 << s["n_open"], dtype=torch.float64, device="cuda")
@@ -368,6 +374,7 @@ def main():
                    "branch_merge": args.branch_merge,
                    "tune_cache": os.path.relpath(args.tune_cache, ROOT) if args.tune_cache else None,
                    "launch": "graph replay per launch group" if args.launch == "graph" else "eager",
+                   "lanes": args.lanes,
                    "events_pass_groups": main_run["events_groups"]},
         "pct_mfma_peak": m["pct_of_form_mfma_peak"],
         "amplitudes_per_s": m.get("measured_amplitudes_per_s", m["projected_amplitudes_per_s"]),

@@ -153,6 +153,8 @@ typedef struct {
     double predicted_ms;          /* learned model's predicted time of the whole job (0 if unused) */
     uint64_t graph_replays;       /* launch groups replayed from captured graphs on this plan so far */
     uint64_t graph_launches;      /* graph launches that replayed them (up to 16 groups per launch) */
+    int32_t lanes;                /* concurrent lanes of launch groups (tn_plan_set_lanes) */
+    uint64_t lanes_workspace_bytes; /* ws_bytes for tn_contract_slices to use every lane */
 } tn_plan_stats;
 
 typedef struct {
@@ -204,9 +206,10 @@ tn_status tn_plan_export_json(tn_plan_t p, char* buf, size_t cap, size_t* need);
  * Runs of at least two full launch groups (2^batch_log2 slices each) replay
  * one captured HIP graph; other groups, and every group while per-step
  * profiling is on, are launched one kernel at a time (same kernels, bitwise
- * equal results).  d_workspace must hold stats.workspace_bytes.  The first
- * call on a device uploads the plan's leaves and computes its
- * slice-invariant subtrees.  Asynchronous on hip_stream.
+ * equal results).  d_workspace must hold stats.workspace_bytes (with
+ * lanes, see tn_plan_set_lanes).  The first call on a device uploads the
+ * plan's leaves and computes its slice-invariant subtrees.  Asynchronous on
+ * hip_stream.
  * Errors: TN_EINVAL (range, sizes, NULL), TN_EDEVICE. */
 tn_status tn_contract_slices(tn_plan_t p, void* d_workspace, size_t ws_bytes,
                              double* d_acc, uint64_t slice_begin, uint64_t slice_end,
@@ -323,6 +326,27 @@ typedef struct {
     uint64_t launches;
     char kernel_name[48];                 /* device function name as profilers show it */
 } tn_step_profile;
+
+/* Run later tn_contract_slices calls on `lanes` concurrent HIP streams
+ * (1 .. 8; default 1).  Section "The algorithm": the subtasks of a sliced
+ * network are independent, so runs of launch groups can execute at once; two
+ * lanes let one lane's bandwidth-bound steps overlap another's
+ * compute-bound ones.  A call with at least two full launch groups per lane
+ * splits its groups into contiguous runs, one per lane: lane 0 runs on the
+ * caller's stream with the caller's accumulator and workspace, lane i on a
+ * private stream (default priority) at d_workspace + i * stride (stride =
+ * stats.workspace_bytes rounded up to 256 bytes) with a private float64
+ * accumulator; the caller's stream then waits for every lane and adds the
+ * lanes' sums in lane order, so results are deterministic for a given lane
+ * count and equal to the one-lane result up to float64 rounding of the
+ * order of the additions.  A call uses as many lanes as whole workspaces fit
+ * in ws_bytes (stats.lanes_workspace_bytes fits all); step timing, slice
+ * lists and short ranges use one lane.  Each extra lane allocates, on its
+ * first use, its stream, 2^acc_log2 complex128 and a few bytes of device
+ * memory, and captures its own graphs; lowering the count releases the
+ * extra lanes after their work has finished.  Errors: TN_EINVAL (range),
+ * TN_EDEVICE. */
+tn_status tn_plan_set_lanes(tn_plan_t p, int32_t lanes);
 
 /* Enable (1) or disable (0) step timing; enabling resets the counters. */
 tn_status tn_plan_set_profiling(tn_plan_t p, int32_t enable);

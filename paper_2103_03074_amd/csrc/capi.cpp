@@ -114,6 +114,12 @@ tn_status tn_plan_stats_get(tn_plan_t p, tn_plan_stats* out) {
     *out = p->plan.stats;
     out->graph_replays = p->dev.graph_replays;
     out->graph_launches = p->dev.graph_launches;
+    for (const auto& ln : p->dev.lanes) {
+        out->graph_replays += ln->d.graph_replays;
+        out->graph_launches += ln->d.graph_launches;
+    }
+    out->lanes = p->dev.n_lanes;
+    out->lanes_workspace_bytes = tn::lanes_workspace_bytes(p->plan, p->dev.n_lanes);
     return TN_OK;
 }
 
@@ -153,7 +159,7 @@ static tn_status contract_groups(tn_plan_t p, void* ws, size_t ws_bytes, double*
     try {
         std::string e = tn::prepare(p->plan, p->dev, s);
         if (!e.empty()) return fail(TN_EDEVICE, e);
-        return from_err(tn::run_groups(p->plan, p->dev, ws, acc, groups, s));
+        return from_err(tn::run_lanes(p->plan, p->dev, ws, ws_bytes, acc, groups, s));
     } catch (const std::bad_alloc&) {
         return fail(TN_ENOMEM, "host allocation failed");
     }
@@ -397,6 +403,16 @@ tn_status tn_xeb(const double* d_amps, int32_t n_open, int32_t n_qubits, double 
         }
     }
     return done(TN_OK);
+}
+
+tn_status tn_plan_set_lanes(tn_plan_t p, int32_t lanes) {
+    if (!p) return fail(TN_EINVAL, "plan is NULL");
+    if (lanes < 1 || lanes > tn::kMaxLanes) return fail(TN_EINVAL, "lanes out of range");
+    try {
+        return from_err(tn::set_lanes(p->plan, p->dev, lanes));
+    } catch (const std::bad_alloc&) {
+        return fail(TN_ENOMEM, "host allocation failed");
+    }
 }
 
 tn_status tn_plan_set_profiling(tn_plan_t p, int32_t enable) {

@@ -256,6 +256,10 @@ static std::string drop_graph(DeviceState& d, int which) {
 static std::string drop_graphs(DeviceState& d) {
     std::string e = drop_graph(d, 0);
     std::string e1 = drop_graph(d, 1);
+    for (auto& ln : d.lanes) {
+        std::string el = drop_graphs(ln->d);
+        if (e1.empty()) e1 = el;
+    }
     return e.empty() ? e1 : e;
 }
 
@@ -546,6 +550,93 @@ std::string run_groups_eager(Plan& p, DeviceState& d, void* ws, double* acc, con
     return err;
 }
 
+// ---------------------------------------------------------------- lanes
+
+static void release_lane(Lane& ln);
+
+uint64_t lane_stride(const Plan& p) { return (p.stats.workspace_bytes + 255) & ~uint64_t(255); }
+
+uint64_t lanes_workspace_bytes(const Plan& p, int n) {
+    return (uint64_t)std::max(0, n - 1) * lane_stride(p) + p.stats.workspace_bytes;
+}
+
+std::string set_lanes(Plan& p, DeviceState& d, int n) {
+    if (n < 1 || n > kMaxLanes) return "lanes out of range (1.." + std::to_string(kMaxLanes) + ")";
+    (void)p;
+    d.n_lanes = n;
+    while ((int)d.lanes.size() > n - 1) {
+        release_lane(*d.lanes.back());
+        d.lanes.pop_back();
+    }
+    return "";
+}
+
+// Lanes 1 .. n-1 on the plan's device, made once.
+static std::string make_lanes(Plan& p, DeviceState& d, int n) {
+    if (!d.fork) TN_HIP(hipEventCreateWithFlags(&d.fork, hipEventDisableTiming));
+    while ((int)d.lanes.size() < n - 1) {
+        d.lanes.push_back(std::make_unique<Lane>());
+        Lane& ln = *d.lanes.back();
+        DeviceState& x = ln.d;
+        x.device = d.device;
+        x.plan_mem = d.plan_mem;
+        x.plan_bytes = d.plan_bytes;
+        x.mask_words = d.mask_words;
+        x.prepared = true;
+        if (d.d_max) TN_HIP(hipMalloc(&x.d_max, sizeof(float) * p.tree.n_nodes()));
+        TN_HIP(hipMalloc(&x.d_state, sizeof(GroupState)));
+        TN_HIP(hipMemset(x.d_state, 0, sizeof(GroupState)));
+        TN_HIP(hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking));
+        TN_HIP(hipEventCreateWithFlags(&ln.join, hipEventDisableTiming));
+        ln.acc_n = 1ull << p.root_log2;
+        TN_HIP(hipMalloc(&ln.acc, 16 * ln.acc_n));
+    }
+    return "";
+}
+
+std::string run_lanes(Plan& p, DeviceState& d, void* ws, size_t ws_bytes, double* acc,
+                      const std::vector<Group>& groups, hipStream_t s) {
+    int L = d.n_lanes;
+    const uint64_t stride = lane_stride(p);
+    if (ws_bytes < p.stats.workspace_bytes) return "workspace too small";
+    L = (int)std::min<uint64_t>((uint64_t)L, 1 + (ws_bytes - p.stats.workspace_bytes) / stride);
+    bool plain = !d.prof.on;
+    for (const Group& g : groups) plain = plain && g.mask.empty();
+    if (L < 2 || !plain || groups.size() < 2 * (size_t)L) return run_groups(p, d, ws, acc, groups, s);
+    std::string err = make_lanes(p, d, L);
+    if (!err.empty()) return err;
+    const size_t n = groups.size();
+    auto part = [&](int i) {
+        return std::vector<Group>(groups.begin() + (n * i) / L, groups.begin() + (n * (i + 1)) / L);
+    };
+    TN_HIP(hipEventRecord(d.fork, s));
+    for (int i = 1; i < L; ++i) {
+        Lane& ln = *d.lanes[i - 1];
+        TN_HIP(hipStreamWaitEvent(ln.stream, d.fork, 0));
+        // the static max slots (leaves, slice-invariant tensors) as the plan has them now
+        if (d.d_max && p.n_static_slots > 0)
+            TN_HIP(hipMemcpyAsync(ln.d.d_max, d.d_max, sizeof(float) * p.n_static_slots, hipMemcpyDeviceToDevice,
+                                  ln.stream));
+        TN_HIP(launch_acc_zero(ln.acc, ln.acc_n, ln.stream));
+    }
+    err = run_groups(p, d, ws, acc, part(0), s);
+    for (int i = 1; i < L && err.empty(); ++i) {
+        Lane& ln = *d.lanes[i - 1];
+        err = run_groups(p, ln.d, (unsigned char*)ws + (uint64_t)i * stride, ln.acc, part(i), ln.stream);
+        if (err.empty()) {
+            hipError_t e = hipEventRecord(ln.join, ln.stream);
+            if (e != hipSuccess) err = std::string("hipEventRecord: ") + hipGetErrorString(e);
+        }
+    }
+    if (!err.empty()) return err;
+    for (int i = 1; i < L; ++i) {
+        Lane& ln = *d.lanes[i - 1];
+        TN_HIP(hipStreamWaitEvent(s, ln.join, 0));
+        TN_HIP(launch_acc_add(acc, ln.acc, ln.acc_n, s));
+    }
+    return "";
+}
+
 // ------------------------------------------------------------- autotune
 
 namespace {
@@ -729,7 +820,20 @@ std::string set_step_kernel(Plan& p, DeviceState& d, int step, int kernel, int t
     return drop_graphs(d);   // the captured graphs used the old choice
 }
 
+static void release_lane(Lane& ln) {
+    if (ln.stream) (void)hipStreamSynchronize(ln.stream);
+    ln.d.plan_mem = nullptr;   // the plan's, freed with the plan's state
+    release(ln.d);
+    if (ln.join) (void)hipEventDestroy(ln.join);
+    if (ln.stream) (void)hipStreamDestroy(ln.stream);
+    if (ln.acc) (void)hipFree(ln.acc);
+    ln = Lane();
+}
+
 void release(DeviceState& d) {
+    for (auto& ln : d.lanes) release_lane(*ln);
+    d.lanes.clear();
+    if (d.fork) (void)hipEventDestroy(d.fork);
     (void)drop_graphs(d);
     if (d.g_done) (void)hipEventDestroy(d.g_done);
     if (d.cap_stream) (void)hipStreamDestroy(d.cap_stream);

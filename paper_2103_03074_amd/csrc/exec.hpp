@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
@@ -20,6 +21,8 @@ struct Profiler {
     std::vector<uint64_t> launches;
     std::vector<std::string> names;
 };
+
+struct Lane;
 
 struct DeviceState {
     int device = -1;
@@ -42,6 +45,22 @@ struct DeviceState {
     uint64_t graph_replays = 0;        // statistics: launch groups replayed from graphs
     uint64_t graph_launches = 0;       // and graph launches
     Profiler prof;
+    // concurrent lanes of launch groups (set_lanes): lane 0 is this state on
+    // the caller's stream, lanes 1 .. n_lanes - 1 are made on first use
+    int n_lanes = 1;
+    hipEvent_t fork = nullptr;
+    std::vector<std::unique_ptr<Lane>> lanes;
+};
+
+// An extra lane: its own stream, workspace slice, max slots, group state,
+// graphs and float64 accumulator; the plan memory (leaves and slice-invariant
+// tensors) is the plan's, read only.
+struct Lane {
+    DeviceState d;
+    hipStream_t stream = nullptr;
+    hipEvent_t join = nullptr;
+    double* acc = nullptr;
+    uint64_t acc_n = 0;   // complex128 entries
 };
 
 struct Group {
@@ -59,6 +78,21 @@ std::string set_step_kernel(Plan& p, DeviceState& d, int step, int kernel, int t
 std::string upload_leaf(Plan& p, DeviceState& d, int leaf, std::vector<cd> data, hipStream_t s);
 std::string run_groups(Plan& p, DeviceState& d, void* ws, double* acc, const std::vector<Group>& groups,
                        hipStream_t s);
+// Workspace bytes between lanes (stats.workspace_bytes rounded up to 256) and
+// the bytes n lanes need.
+uint64_t lane_stride(const Plan& p);
+uint64_t lanes_workspace_bytes(const Plan& p, int n);
+// Number of lanes of later calls (1 .. kMaxLanes); fewer releases the extra
+// lanes (after their work has finished).
+constexpr int kMaxLanes = 8;
+std::string set_lanes(Plan& p, DeviceState& d, int n);
+// run_groups over as many lanes as are set and fit in ws_bytes: the groups
+// are split into contiguous runs, one per lane, run concurrently; the
+// caller's stream waits for every lane and adds the lanes' sums to acc in
+// lane order.  One lane (run_groups itself) while step timing is on, for
+// slice lists, or with fewer than two groups per lane.
+std::string run_lanes(Plan& p, DeviceState& d, void* ws, size_t ws_bytes, double* acc,
+                      const std::vector<Group>& groups, hipStream_t s);
 void release(DeviceState& d);
 std::string profile_enable(Plan& p, DeviceState& d, bool on);
 std::string profile_harvest(DeviceState& d);

@@ -65,6 +65,9 @@ hipError_t launch_slice_sum(int storage, const void* root, double* acc, int res_
                             const uint64_t* d_slice = nullptr, const uint8_t* r_bit = nullptr,
                             const uint8_t* r_pos = nullptr, int r_n = 0);
 hipError_t launch_copy_acc(const double* src, double* dst, uint64_t n, hipStream_t s);
+// acc[i] += part[i] and acc[i] = 0 over n complex128 entries (lanes.hip)
+hipError_t launch_acc_add(double* acc, const double* part, uint64_t n, hipStream_t s);
+hipError_t launch_acc_zero(double* acc, uint64_t n, hipStream_t s);
 hipError_t launch_xeb_partials(const double* amps, uint64_t n, double w, double* part, int blocks,
                                hipStream_t s);
 hipError_t launch_xeb_cond(const double* amps, uint64_t n, double w, double inv_sum, double* part,

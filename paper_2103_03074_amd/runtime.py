@@ -11,9 +11,10 @@ from . import tn
 
 
 def workspace(plan, device=None):
-    """Workspace for tn_contract_slices and tn_amplitudes (the larger need)."""
+    """Workspace for tn_contract_slices (every lane the plan is set to use)
+    and tn_amplitudes: the larger need."""
     s = plan.stats()
-    n = max(int(s["workspace_bytes"]), int(s["tail_workspace_bytes"]), 256)
+    n = max(int(s["lanes_workspace_bytes"]), int(s["tail_workspace_bytes"]), 256)
     return torch.empty(n, dtype=torch.uint8, device=device or "cuda")
 
 

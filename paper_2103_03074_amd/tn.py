@@ -68,7 +68,8 @@ class PlanStats(ctypes.Structure):
                 ("n_dense_steps", ctypes.c_int32), ("n_small_steps", ctypes.c_int32),
                 ("cost_model_used", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
                 ("predicted_ms", ctypes.c_double), ("graph_replays", ctypes.c_uint64),
-                ("graph_launches", ctypes.c_uint64)]
+                ("graph_launches", ctypes.c_uint64), ("lanes", ctypes.c_int32),
+                ("lanes_workspace_bytes", ctypes.c_uint64)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -130,6 +131,7 @@ _SIGS = {
                                    ctypes.c_uint64, _P, ctypes.c_uint64, _P, _P, ctypes.c_size_t,
                                    ctypes.POINTER(MixResult), _P]),
     "tn_sample_noalloc": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P]),
+    "tn_plan_set_lanes": (ctypes.c_int, [_P, ctypes.c_int32]),
     "tn_plan_set_profiling": (ctypes.c_int, [_P, ctypes.c_int32]),
     "tn_plan_step_profile": (ctypes.c_int, [_P, ctypes.POINTER(StepProfile), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
@@ -279,6 +281,9 @@ class Plan:
         buf = ctypes.create_string_buffer(need.value)
         _check(library().tn_plan_export_json(self.handle, buf, need.value, ctypes.byref(need)))
         return json.loads(buf.value.decode())
+
+    def set_lanes(self, lanes):
+        _check(library().tn_plan_set_lanes(self.handle, int(lanes)))
 
     def set_profiling(self, enable):
         _check(library().tn_plan_set_profiling(self.handle, 1 if enable else 0))

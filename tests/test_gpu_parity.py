@@ -832,3 +832,87 @@ def test_c3_many_group_graph_closed_form():
               for j in range(lo, hi))
     _check(got, ref, C128_TOL, "c3 many-group graph", skewed=True)
 
+
+
+# --- concurrent lanes of launch groups (tn_plan_set_lanes) ------------------
+
+def _lanes_acc(p, lanes, ws, lo, hi):
+    torch = _torch()
+    from paper_2103_03074_amd import runtime
+    p.set_lanes(lanes)
+    acc = runtime.accumulator(p)
+    p.contract_slices(ws, acc, lo, hi)
+    torch.cuda.synchronize()
+    return acc.cpu().numpy().view(np.complex128)
+
+
+def test_lanes_c2_vs_one_lane_and_statevector(c2_state):
+    """64 launch groups of the 25-qubit plan split over 2 and 3 lanes: every
+    group replayed from the lanes' graphs, bitwise repeatable per lane count,
+    equal to one lane up to float64 rounding of the order of the sums, and
+    against the state vector; a workspace for one lane runs one lane."""
+    torch = _torch()
+    from paper_2103_03074_amd import runtime
+    w, psi = c2_state
+    p = _plan(w, n_slice_edges=8, restarts=4, batch_log2=2)
+    p.set_lanes(3)
+    ws = runtime.workspace(p)
+    assert ws.numel() >= p.stats()["lanes_workspace_bytes"]
+    ref = sv.amplitudes_from_state(psi, 25, w["open_q"], w["fixed_q"], w["bits"])
+    _say("c2 lanes: one lane")
+    one = _lanes_acc(p, 1, ws, 0, 256)
+    _check(one, ref, C64_TOL, "c2 one lane")
+    for lanes in (2, 3):
+        _say("c2 lanes:", lanes)
+        r0 = p.stats()["graph_replays"]
+        a = _lanes_acc(p, lanes, ws, 0, 256)
+        b = _lanes_acc(p, lanes, ws, 0, 256)
+        np.testing.assert_array_equal(a, b)
+        assert p.stats()["graph_replays"] - r0 == 2 * 64
+        assert _rel(a, one) < 1e-13, _rel(a, one)
+        _check(a, ref, C64_TOL, "c2 lanes", lanes)
+    ws1 = torch.empty(p.stats()["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    _say("c2 lanes: 2 lanes set, workspace for one")
+    np.testing.assert_array_equal(_lanes_acc(p, 2, ws1, 0, 256), one)
+    p.set_lanes(1)
+
+
+def test_lanes_c3_closed_form():
+    """Two lanes over 8 full launch groups (2^4 slices each) of the 40-qubit
+    plan in complex128 against the closed form of the 128 slices (product-gate
+    vehicle), so an indexing or workspace-offset error in a lane shows at
+    1e-12."""
+    from paper_2103_03074_amd import runtime
+    w = rqc.workload("c3_5x8_m16", two_qubit="product")
+    p = _c3_plan(w, prec="c128", batch_log2=4)
+    assert p.stats()["batch_log2"] == 4
+    sliced = p.sliced_edges()
+    lo, hi = 3 << 4, (3 + 8) << 4
+    p.set_lanes(2)
+    ws = runtime.workspace(p)
+    _say("c3 lanes c128, slices", lo, hi)
+    got = _lanes_acc(p, 2, ws, lo, hi)
+    assert p.stats()["graph_replays"] == 8
+    ref = sum(cf.product_amplitudes(w["circuit"], w["open_q"], w["fixed_q"], w["bits"], sliced, j)
+              for j in range(lo, hi))
+    _check(got, ref, C128_TOL, "c3 lanes closed form", skewed=True)
+
+
+@pytest.mark.parametrize("prec", ["c64", "split_fp16"])
+def test_lanes_c3_bench_plan_vs_one_lane(prec):
+    """The bench's plan over 4 full launch groups (2^8 slices each) on two
+    lanes against one lane: the mixed form reads the leaves' and the
+    slice-invariant tensors' max slots in every lane."""
+    from paper_2103_03074_amd import runtime
+    w = rqc.workload("c3_5x8_m16")
+    p = _c3_plan(w, prec=prec)
+    B = 1 << p.stats()["batch_log2"]
+    p.set_lanes(2)
+    ws = runtime.workspace(p)
+    _say("c3 lanes", prec, "one lane")
+    one = _lanes_acc(p, 1, ws, 0, 4 * B)
+    _say("c3 lanes", prec, "two lanes")
+    two = _lanes_acc(p, 2, ws, 0, 4 * B)
+    err = _rel(two, one)
+    _say("c3 lanes", prec, "two vs one lane norm-rel", f"{err:.3e}")
+    assert err < 1e-12, err

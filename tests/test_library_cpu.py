@@ -234,3 +234,24 @@ def test_open_qubits_read_off_the_order():
         with pytest.raises(tn.TnError) as ei:
             tn.choose_open_qubits(w["circuit"], bad)
         assert ei.value.status == -1
+
+
+def test_lanes_setting_and_workspace_size():
+    """tn_plan_set_lanes: range checks and the workspace the lanes need
+    (lane i at i * stride, stride = workspace_bytes rounded up to 256)."""
+    _, p = _plan("c1_tiny_3x4_m8", n_slice_edges=2)
+    s = p.stats()
+    assert s["lanes"] == 1 and s["lanes_workspace_bytes"] == s["workspace_bytes"]
+    stride = (s["workspace_bytes"] + 255) // 256 * 256
+    for n in (2, 3, 8):
+        p.set_lanes(n)
+        s = p.stats()
+        assert s["lanes"] == n
+        assert s["lanes_workspace_bytes"] == (n - 1) * stride + s["workspace_bytes"]
+    for bad in (0, -1, 9):
+        with pytest.raises(tn.TnError) as ei:
+            p.set_lanes(bad)
+        assert ei.value.status == -1
+    assert p.stats()["lanes"] == 8
+    p.set_lanes(1)
+    assert p.stats()["lanes_workspace_bytes"] == p.stats()["workspace_bytes"]
