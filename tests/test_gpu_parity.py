@@ -916,3 +916,32 @@ def test_lanes_c3_bench_plan_vs_one_lane(prec):
     err = _rel(two, one)
     _say("c3 lanes", prec, "two vs one lane norm-rel", f"{err:.3e}")
     assert err < 1e-12, err
+
+
+def test_lanes_bighead_c2_vs_one_lane_and_statevector(c2_state):
+    """Big-head split of the 25-qubit workload with launch groups of 2^1
+    slices: the head's groups on two lanes (the accumulator is v_head), then
+    the tail; equal to one lane up to float64 rounding and against the state
+    vector."""
+    torch = _torch()
+    from paper_2103_03074_amd import runtime
+    w, psi = c2_state
+    p = _plan(w, bighead=1, restarts=4, max_log2_size=22, batch_log2=1)
+    s = p.stats()
+    n = s["n_slices"]
+    _say("c2 bighead lanes: n_c", s["n_c"], "slices", n, "groups", n >> s["batch_log2"])
+    assert (n >> s["batch_log2"]) >= 4
+    p.set_lanes(2)
+    ws = runtime.workspace(p)
+    amps = torch.empty(2 << s["n_open"], dtype=torch.float64, device="cuda")
+    out = []
+    for lanes in (1, 2):
+        p.set_lanes(lanes)
+        acc = runtime.accumulator(p)
+        p.contract_slices(ws, acc, 0, n)
+        p.amplitudes(acc, amps, ws)
+        torch.cuda.synchronize()
+        out.append(torch.view_as_complex(amps.view(-1, 2)).cpu().numpy().copy())
+    assert _rel(out[1], out[0]) < 1e-13, _rel(out[1], out[0])
+    ref = sv.amplitudes_from_state(psi, 25, w["open_q"], w["fixed_q"], w["bits"])
+    _check(out[1], ref, C64_TOL, "c2 bighead two lanes")
