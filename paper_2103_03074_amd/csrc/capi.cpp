@@ -409,7 +409,7 @@ tn_status tn_plan_set_lanes(tn_plan_t p, int32_t lanes) {
     if (!p) return fail(TN_EINVAL, "plan is NULL");
     if (lanes < 1 || lanes > tn::kMaxLanes) return fail(TN_EINVAL, "lanes out of range");
     try {
-        return from_err(tn::set_lanes(p->plan, p->dev, lanes));
+        return from_err(tn::set_lanes(p->dev, lanes));
     } catch (const std::bad_alloc&) {
         return fail(TN_ENOMEM, "host allocation failed");
     }

@@ -560,9 +560,8 @@ uint64_t lanes_workspace_bytes(const Plan& p, int n) {
     return (uint64_t)std::max(0, n - 1) * lane_stride(p) + p.stats.workspace_bytes;
 }
 
-std::string set_lanes(Plan& p, DeviceState& d, int n) {
+std::string set_lanes(DeviceState& d, int n) {
     if (n < 1 || n > kMaxLanes) return "lanes out of range (1.." + std::to_string(kMaxLanes) + ")";
-    (void)p;
     d.n_lanes = n;
     while ((int)d.lanes.size() > n - 1) {
         release_lane(*d.lanes.back());
@@ -571,25 +570,36 @@ std::string set_lanes(Plan& p, DeviceState& d, int n) {
     return "";
 }
 
-// Lanes 1 .. n-1 on the plan's device, made once.
+// One extra lane on the plan's device.
+static std::string init_lane(Plan& p, const DeviceState& d, Lane& ln) {
+    DeviceState& x = ln.d;
+    x.device = d.device;
+    x.plan_mem = d.plan_mem;
+    x.plan_bytes = d.plan_bytes;
+    x.mask_words = d.mask_words;
+    x.prepared = true;
+    if (d.d_max) TN_HIP(hipMalloc(&x.d_max, sizeof(float) * p.tree.n_nodes()));
+    TN_HIP(hipMalloc(&x.d_state, sizeof(GroupState)));
+    TN_HIP(hipMemset(x.d_state, 0, sizeof(GroupState)));
+    TN_HIP(hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking));
+    TN_HIP(hipEventCreateWithFlags(&ln.join, hipEventDisableTiming));
+    ln.acc_n = 1ull << p.root_log2;
+    TN_HIP(hipMalloc(&ln.acc, 16 * ln.acc_n));
+    return "";
+}
+
+// Lanes 1 .. n-1, made once; a lane that fails to initialise is released
+// and not kept.
 static std::string make_lanes(Plan& p, DeviceState& d, int n) {
     if (!d.fork) TN_HIP(hipEventCreateWithFlags(&d.fork, hipEventDisableTiming));
     while ((int)d.lanes.size() < n - 1) {
-        d.lanes.push_back(std::make_unique<Lane>());
-        Lane& ln = *d.lanes.back();
-        DeviceState& x = ln.d;
-        x.device = d.device;
-        x.plan_mem = d.plan_mem;
-        x.plan_bytes = d.plan_bytes;
-        x.mask_words = d.mask_words;
-        x.prepared = true;
-        if (d.d_max) TN_HIP(hipMalloc(&x.d_max, sizeof(float) * p.tree.n_nodes()));
-        TN_HIP(hipMalloc(&x.d_state, sizeof(GroupState)));
-        TN_HIP(hipMemset(x.d_state, 0, sizeof(GroupState)));
-        TN_HIP(hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking));
-        TN_HIP(hipEventCreateWithFlags(&ln.join, hipEventDisableTiming));
-        ln.acc_n = 1ull << p.root_log2;
-        TN_HIP(hipMalloc(&ln.acc, 16 * ln.acc_n));
+        auto ln = std::make_unique<Lane>();
+        std::string err = init_lane(p, d, *ln);
+        if (!err.empty()) {
+            release_lane(*ln);
+            return err;
+        }
+        d.lanes.push_back(std::move(ln));
     }
     return "";
 }

@@ -85,7 +85,7 @@ uint64_t lanes_workspace_bytes(const Plan& p, int n);
 // Number of lanes of later calls (1 .. kMaxLanes); fewer releases the extra
 // lanes (after their work has finished).
 constexpr int kMaxLanes = 8;
-std::string set_lanes(Plan& p, DeviceState& d, int n);
+std::string set_lanes(DeviceState& d, int n);
 // run_groups over as many lanes as are set and fit in ws_bytes: the groups
 // are split into contiguous runs, one per lane, run concurrently; the
 // caller's stream waits for every lane and adds the lanes' sums to acc in
