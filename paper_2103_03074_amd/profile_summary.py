@@ -21,6 +21,12 @@ Inputs are the directories written by `rocprofv3 --output-format csv -d DIR`:
   are averaged per dispatch of each kernel and tabulated in
   `<out>_counters.txt`.
 
+With `--overlap` instead of the counter runs, one `--kernel-trace` run of
+the bench on several lanes is summarised as concurrency: the timed window,
+the summed kernel durations, the time at least one and at least two kernels
+were running, and each kernel's average duration under overlap, written to
+`<out>_lanes_overlap.txt`.
+
 The JSON records the SHA-256 of the kernel source the counters were taken
 with (`--source-sha-file`, written next to the CSV files by the profiling
 commands), so a reader can tell when the figures are stale.
@@ -111,6 +117,39 @@ def trace_table(directory):
     return sorted(rows, key=lambda r: -r["total_us"])
 
 
+def overlap_summary(directory):
+    """Concurrency of the bracketed dispatches: window, summed durations,
+    time with >= 1 and >= 2 kernels running (us), and per-kernel averages."""
+    ds = []
+    for r in read_csv(directory, "kernel_trace.csv"):
+        t0 = int(col(r, "Start_Timestamp"))
+        t1 = int(col(r, "End_Timestamp"))
+        ds.append((int(col(r, "Dispatch_Id")), short_name(col(r, "Kernel_Name")), (t0, t1)))
+    inner, _ = bracketed(ds, lambda iv: iv[1] - iv[0])
+    events = []
+    for _, _, (t0, t1) in inner:
+        events += [(t0, 1), (t1, -1)]
+    events.sort()
+    busy1 = busy2 = 0
+    depth, last = 0, None
+    for t, d in events:
+        if last is not None and depth >= 1:
+            busy1 += t - last
+            if depth >= 2:
+                busy2 += t - last
+        depth += d
+        last = t
+    window = max(iv[1] for _, _, iv in inner) - min(iv[0] for _, _, iv in inner)
+    total = sum(iv[1] - iv[0] for _, _, iv in inner)
+    agg = collections.defaultdict(list)
+    for _, k, (t0, t1) in inner:
+        agg[k].append((t1 - t0) / 1e3)
+    rows = sorted(({"kernel": k, "calls": len(v), "total_us": sum(v), "avg_us": sum(v) / len(v)}
+                   for k, v in agg.items()), key=lambda r: -r["total_us"])
+    return {"window_us": window / 1e3, "sum_us": total / 1e3, "busy1_us": busy1 / 1e3, "busy2_us": busy2 / 1e3,
+            "dispatches": len(inner)}, rows
+
+
 def counter_table(directory, copy_kib=None):
     """Per kernel: {counter: mean value per dispatch} over the bracketed
     dispatches, the dispatch count, and (when copy_kib is given) the factor of
@@ -159,9 +198,10 @@ def bench_record(path):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--trace", default="")
+    ap.add_argument("--fetch", default="")
+    ap.add_argument("--write", default="")
+    ap.add_argument("--overlap", default="", help="kernel-trace run of the bench on several lanes")
     ap.add_argument("--extra", action="append", default=[], help="further --pmc run directories")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--bench-json", default="")
@@ -172,6 +212,25 @@ def main():
                     help="sha256sum output for kernels.hip written on the profiled machine")
     args = ap.parse_args()
     cmd_lines = ["Commands:", ""] + ["    " + c for c in args.command.split(" ;; ") if c]
+    if args.overlap:
+        o, rows = overlap_summary(args.overlap)
+        lines = [f"# Kernel concurrency, timed steps only: {args.title}", ""] + cmd_lines + [""]
+        lines += [f"dispatches {o['dispatches']}; timed window {o['window_us']:.1f} us; summed kernel durations "
+                  f"{o['sum_us']:.1f} us ({o['sum_us'] / o['window_us']:.2f}x the window); at least one kernel "
+                  f"running {o['busy1_us']:.1f} us ({100 * o['busy1_us'] / o['window_us']:.1f} %); at least two "
+                  f"{o['busy2_us']:.1f} us ({100 * o['busy2_us'] / o['window_us']:.1f} %).", "",
+                  "Durations under overlap (two kernels share the GPU, so these are not kernel speeds):", "",
+                  f"{'kernel':48s} {'calls':>7s} {'total us':>12s} {'avg us':>10s}"]
+        for r in rows:
+            if r["total_us"] < 1e-3 * o["sum_us"]:
+                continue
+            lines.append(f"{r['kernel'][:48]:48s} {r['calls']:7d} {r['total_us']:12.1f} {r['avg_us']:10.2f}")
+        with open(args.out + "_lanes_overlap.txt", "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        return
+    if not (args.trace and args.fetch and args.write):
+        raise SystemExit("--trace, --fetch and --write are required (or --overlap)")
 
     tr = trace_table(args.trace)
     lines = [f"# Kernel trace, timed steps only: {args.title}", ""] + cmd_lines

@@ -255,3 +255,25 @@ def test_lanes_setting_and_workspace_size():
     assert p.stats()["lanes"] == 8
     p.set_lanes(1)
     assert p.stats()["lanes_workspace_bytes"] == p.stats()["workspace_bytes"]
+
+
+def test_profile_overlap_summary(tmp_path):
+    """profile_summary's concurrency figures on a hand-made kernel trace: two
+    bracketing copies, then kernels a [0, 10), b [5, 20), c [30, 40) (us)
+    between them: window 40, summed 35, busy 30, two at once 5."""
+    import csv
+    from paper_2103_03074_amd import profile_summary as ps
+    rows = [(1, ps.COPY_KERNEL, -100, -50), (2, "void tn::a(tn::GemmArgs)", 0, 10),
+            (3, "void tn::b(tn::GemmArgs)", 5, 20), (4, "void tn::c(tn::GemmArgs)", 30, 40),
+            (5, ps.COPY_KERNEL, 100, 150)]
+    d = tmp_path / "run"
+    d.mkdir()
+    with open(d / "1_kernel_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        for i, k, t0, t1 in rows:
+            w.writerow([i, k, t0 * 1000, t1 * 1000])
+    o, table = ps.overlap_summary(str(d))
+    assert o["dispatches"] == 3
+    assert (o["window_us"], o["sum_us"], o["busy1_us"], o["busy2_us"]) == (40.0, 35.0, 30.0, 5.0)
+    assert [r["kernel"] for r in table] == ["b", "a", "c"]
