@@ -945,3 +945,27 @@ def test_lanes_bighead_c2_vs_one_lane_and_statevector(c2_state):
     assert _rel(out[1], out[0]) < 1e-13, _rel(out[1], out[0])
     ref = sv.amplitudes_from_state(psi, 25, w["open_q"], w["fixed_q"], w["bits"])
     _check(out[1], ref, C64_TOL, "c2 bighead two lanes")
+
+
+@pytest.mark.parametrize("prec", ["c64", "split_fp16"])
+def test_lanes_c3_random_circuit_vs_oracle(prec):
+    """Two lanes of 2 full launch groups each (2^2 slices per group) of the
+    40-qubit random circuit, through the lanes' captured graphs, against the
+    oracle's complex128 sum of the same 16 slices."""
+    from paper_2103_03074_amd import runtime
+    w = rqc.workload("c3_5x8_m16")
+    p = _c3_plan(w, batch_log2=2, prec=prec)
+    assert p.stats()["batch_log2"] == 2
+    ex = p.export()
+    sliced = [tuple(e) for e in ex["sliced"]]
+    tree = list(zip(ex["lhs"], ex["rhs"]))
+    net = nw.build_network(w["circuit"], w["open_q"], w["fixed_q"], w["bits"])
+    g0 = int(rqc.sample_slice_ids(14, 1, seed=8)[0]) % (2 ** 14 - 4)
+    lo, hi = 4 * g0, 4 * g0 + 16
+    p.set_lanes(2)
+    ws = runtime.workspace(p)
+    _say("c3 lanes random circuit", prec, "slices", lo, hi)
+    got = _lanes_acc(p, 2, ws, lo, hi)
+    assert p.stats()["graph_replays"] == 4
+    ref = sum(nw.contract(nw.slice_network(net, sliced, nw.slice_values(sliced, j)), tree) for j in range(lo, hi))
+    _check(got, ref, C64_TOL if prec == "c64" else MIXED_TOL[prec], "c3 lanes vs oracle", prec)
